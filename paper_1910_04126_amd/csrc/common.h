@@ -1,0 +1,179 @@
+// Internal declarations shared by the ftree HIP sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/ftree.h"
+
+namespace ft {
+
+// ---------------------------------------------------------------- errors --
+
+struct Error : std::runtime_error {
+  ft_status status;
+  Error(ft_status s, const std::string& m) : std::runtime_error(m), status(s) {}
+};
+
+void set_last_error(const std::string& msg);
+
+#define FT_HIP(call)                                                          \
+  do {                                                                        \
+    hipError_t e_ = (call);                                                   \
+    if (e_ != hipSuccess)                                                     \
+      throw ::ft::Error(FT_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define FT_REQUIRE(cond, status, msg)                          \
+  do {                                                         \
+    if (!(cond)) throw ::ft::Error((status), (msg));           \
+  } while (0)
+
+// Runs f, turning exceptions into an ft_status and the thread's last error.
+template <class F>
+ft_status guarded(F&& f) {
+  try {
+    f();
+    return FT_OK;
+  } catch (const Error& e) {
+    set_last_error(e.what());
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    set_last_error("host allocation failed");
+    return FT_ENOMEM;
+  } catch (const std::exception& e) {
+    set_last_error(e.what());
+    return FT_EHIP;
+  }
+}
+
+// ------------------------------------------------------- device buffers --
+
+// A growable device allocation owned by the index.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  void* ensure(size_t n);
+  void release();
+  template <class T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+// Validation flags written by kernels (device u32 each).
+enum : uint32_t {
+  ERR_ID_RANGE = 1u,
+  ERR_ZERO_MASS = 2u,
+  ERR_MASS_SUM = 4u,
+  ERR_DUPLICATE = 8u,
+  ERR_SIZE = 16u,
+  ERR_EMPTY = 32u,
+  ERR_FLOW = 64u,  // internal consistency of the greedy (must never fire)
+};
+std::string describe_flags(uint32_t f);
+
+// Sorted, validated distributions in Morton-rank order (docs or queries).
+struct Dists {
+  int64_t n = 0, nnz = 0;
+  int32_t max_size = 0;
+  int64_t emb_nnz = 0;
+  DevBuf off;      // int64 [n+1] (copy of the caller's offsets)
+  DevBuf rank;     // u32 [nnz]  Morton ranks, ascending within a distribution
+  DevBuf mass;     // u32 [nnz]
+  DevBuf pos;      // u16 [nnz]  position of the item in the caller's CSR row
+  DevBuf lcp;      // u8  [nnz]  depth of the deepest cell shared with the next item
+  DevBuf ecnt;     // int64 [n+1] embedding offsets
+  DevBuf ekey;     // u32 [emb_nnz] node key: depth << 27 | index within depth
+  DevBuf emass;    // u32 [emb_nnz]
+  DevBuf S;        // u64 [n]  sum of 2^(B-depth) * mass over embedding entries
+  DevBuf tmp;      // scratch for the preparation
+  void release();
+};
+
+struct TuneChoice {
+  int32_t chunk = 4;        // pairs per work grab of the persistent kernel
+  int32_t blocks_per_cu = 0; // 0: from occupancy
+  int32_t classes = 0;       // bitmask of pair-size classes used (0: all)
+};
+
+// Captured graphs of the batched Flowtree path: the bucketing of pairs into
+// size classes, and the persistent launches.  Rebuilt when any baked
+// argument changes.
+struct BatchedGraphs {
+  hipGraphExec_t pre = nullptr, main = nullptr;
+  std::vector<uint64_t> key;
+  void reset();
+};
+
+}  // namespace ft
+
+struct ft_index {
+  int64_t V = 0;
+  int32_t d = 0, dp = 0, B = 0, Q = 0, height = 0, st_levels = 0;
+  int64_t n_nodes = 0;
+  int device = 0;
+  int n_cu = 0;
+  hipStream_t work = nullptr;  // internal stream for graph capture
+  hipEvent_t ev_a = nullptr, ev_b = nullptr, ev_t0 = nullptr, ev_t1 = nullptr;
+  ft::DevBuf Xm;        // float [V * dp], Morton order, rows padded to dp
+  ft::DevBuf perm;      // u32 [V] rank -> original id
+  ft::DevBuf inv;       // u32 [V] original id -> rank
+  ft::DevBuf st;        // u8  [st_levels * V] range-minimum table over adjacent LCA depths
+  ft::DevBuf leafd;     // u8  [V]
+  ft::DevBuf anc;       // u32 [height * V] index of the depth-(k+1) node of each rank
+  ft::DevBuf status;    // u32 [8] validation flags and counters
+  ft::Dists docs;
+  // per-call workspaces
+  ft::Dists qry;
+  ft::DevBuf ws_keys, ws_cost, ws_tiles, ws_lists, ws_counts, ws_misc, ws_sel;
+  ft::DevBuf fwd_id, fwd_eta, fwd_key, fwd_bind, fwd_cnt, fwd_base;  // saved flows (FT_FWD)
+  int64_t fwd_pairs = 0, fwd_cap = 0;
+  ft::DevBuf fwd_sig;          // copies of the FT_FWD query CSR and pairs
+  int64_t fwd_sig_bytes = 0;
+  bool fwd_valid = false;
+  int32_t autotune = 1;
+  std::map<std::string, ft::TuneChoice> tuned;
+  ft::BatchedGraphs graphs;
+  double last_batched_ms = 0.0;
+  std::string last_schedule;
+  std::mutex mu;
+};
+
+namespace ft {
+
+// -------------------------------------------------------- shared device --
+
+constexpr uint32_t KEY_DEPTH_SHIFT = 27;
+constexpr uint32_t KEY_INDEX_MASK = (1u << KEY_DEPTH_SHIFT) - 1u;
+
+// Depth of the deepest cell shared by Morton ranks a <= b: the minimum of
+// the adjacent LCA depths over [a, b), from the range-minimum table.
+__device__ __forceinline__ int lca_depth(const uint8_t* __restrict__ st, int64_t V, int B,
+                                         uint32_t a, uint32_t b) {
+  if (a == b) return B;
+  uint32_t len = b - a;
+  int j = 31 - __clz(len);
+  uint8_t x = st[(int64_t)j * V + a];
+  uint8_t y = st[(int64_t)j * V + (b - (1u << j))];
+  return x < y ? x : y;
+}
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Host helpers implemented in build.hip.
+void prepare_dists(ft_index* ix, Dists& D, const int64_t* off, const uint32_t* id,
+                   const uint32_t* mass, int64_t n, bool with_embedding, hipStream_t s,
+                   const char* what);
+int64_t scan_tmp_elems(int64_t n);
+void exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* tmp, hipStream_t s);
+uint32_t read_and_clear_status(ft_index* ix, hipStream_t s);
+// FT_EINVAL unless every v[i] lies in [0, bound) (synchronises s).
+void check_indices(ft_index* ix, const int64_t* v, int64_t n, int64_t bound, hipStream_t s, const char* what);
+
+}  // namespace ft

@@ -1,0 +1,330 @@
+// Flowtree for one (query, doc) pair on one wavefront (paper Section 3 and
+// Appendix A.1).
+//
+// The greedy processes cells bottom-up; a cell matches the unmatched doc
+// (mu) and query (nu) mass collected from its children and passes the rest
+// up.  Listing both supports in Morton order makes every cell a contiguous
+// run of the merged item list, and the cells of one depth k are the maximal
+// runs whose adjacent LCA depths are >= k.  Cells of equal depth are
+// disjoint, so a whole depth is processed at once:
+//   * inclusive segmented prefix sums P+ (doc mass) and P- (query mass);
+//   * with M = min(total P+, total P-) of the run, the front-to-front
+//     matching of the run's doc items against its query items (both in
+//     Morton order) pairs the overlaps of the intervals [P - r, P) inside
+//     [0, M): every such overlap starts at some item's interval start, so
+//     each item finds the match starting at its own interval start by one
+//     binary search on the other side's prefix sums (a doc item wins a tie);
+//   * an item keeps the part of its interval beyond M.
+// Only depths that occur among the adjacent LCA depths (plus the root) can
+// change anything; the others are skipped.
+//
+// Layout: a wavefront owns NMAX = 64 * C merged items, lane l the items
+// [l*C, l*C + C); per-item state lives in LDS.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "common.h"
+#include "wave.h"
+
+namespace ft {
+
+template <int C>
+struct FlowLds {
+  static constexpr int N = 64 * C;
+  uint32_t rank[N];    // merged Morton ranks
+  uint32_t res[N];     // unmatched mass
+  uint32_t pp[N];      // doc-side inclusive prefix (before the merge: input ranks)
+  uint32_t pn[N];      // query-side inclusive prefix (before the merge: input masses)
+  uint32_t em_pos[N];  // match: merged position of the doc item | query item << 16
+  uint32_t em_eta[N];  // match: integer mass moved
+  uint16_t slot[N];    // merged position -> input slot (query [0, nq), doc [nq, nq + nd))
+  int8_t lcn[N];       // LCA depth of (t, t + 1); -1 after the last item
+};
+
+// Where a saved flow goes (gradient and inspection paths).
+struct FlowSave {
+  uint32_t* id;     // doc slot << 16 | query slot (slots inside each sorted support)
+  uint32_t* eta;
+  uint64_t* key;    // (31 - depth) << 48 | segment start << 32 | interval start
+  uint8_t* bind;    // 0: doc item used up, 1: query item, 2: both
+  int64_t base;
+};
+
+// Stage a pair: query items into slots [0, nq), doc items into [nq, nq + nd).
+template <int C>
+__device__ __forceinline__ void flow_stage(FlowLds<C>& L, const uint32_t* __restrict__ qr,
+                                           const uint32_t* __restrict__ qm, int nq,
+                                           const uint32_t* __restrict__ dr,
+                                           const uint32_t* __restrict__ dm, int nd) {
+  const int lane = lane_id();
+  for (int i = lane; i < nq; i += 64) {
+    L.pp[i] = qr[i];
+    L.pn[i] = qm[i];
+  }
+  for (int i = lane; i < nd; i += 64) {
+    L.pp[nq + i] = dr[i];
+    L.pn[nq + i] = dm[i];
+  }
+  __syncthreads();
+}
+
+// The greedy flow of a staged pair; returns the number of matches in
+// L.em_pos / L.em_eta (uniform across the wavefront).
+template <int C, bool SAVE>
+__device__ int flow_match(FlowLds<C>& L, const int nq, const int nd, const uint8_t* __restrict__ st,
+                          const int64_t V, const int B, FlowSave sv, uint32_t* __restrict__ status) {
+  const int lane = lane_id();
+  const int n = nq + nd;
+  const int t0 = lane * C;
+  // ---- merge both supports by rank (doc first on equal ranks)
+  {
+    const uint32_t* qr = L.pp;
+    const uint32_t* dr = L.pp + nq;
+    const int k0 = min(t0, n);
+    int lo = max(0, k0 - nq), hi = min(k0, nd);
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (dr[mid] <= qr[k0 - mid - 1]) lo = mid + 1;
+      else hi = mid;
+    }
+    int j = lo, i = k0 - lo;
+    for (int c = 0; c < C; ++c) {
+      const int t = t0 + c;
+      if (t < n) {
+        const bool take_d = j < nd && (i >= nq || dr[j] <= qr[i]);
+        const int s = take_d ? nq + j : i;
+        if (take_d) ++j;
+        else ++i;
+        L.rank[t] = L.pp[s];
+        L.res[t] = L.pn[s];
+        L.slot[t] = (uint16_t)s;
+      }
+    }
+  }
+  __syncthreads();
+  // ---- adjacent LCA depths and the depths present
+  uint32_t mask = 1u;
+  for (int c = 0; c < C; ++c) {
+    const int t = t0 + c;
+    if (t < n) {
+      int l = -1;
+      if (t + 1 < n) {
+        l = lca_depth(st, V, B, L.rank[t], L.rank[t + 1]);
+        mask |= 1u << l;
+      }
+      L.lcn[t] = (int8_t)l;
+    }
+  }
+  mask = wave_or(mask);
+  __syncthreads();
+  int E = 0;
+  while (mask) {
+    const int k = 31 - __clz(mask);
+    mask &= ~(1u << k);
+    // local segmented sums of this lane's items
+    uint32_t run_p = 0, run_n = 0;
+    int last_start = -1, first_end = 0x7FFFFFFF;
+    for (int c = 0; c < C; ++c) {
+      const int t = t0 + c;
+      if (t < n) {
+        if (t == 0 || L.lcn[t - 1] < k) {
+          run_p = run_n = 0;
+          last_start = t;
+        }
+        const uint32_t r = L.res[t];
+        if (L.slot[t] < nq) run_n += r;
+        else run_p += r;
+        if (L.lcn[t] < k && first_end == 0x7FFFFFFF) first_end = t;
+      }
+    }
+    uint32_t tp = run_p, tn = run_n;
+    wave_seg_incl_sum2(tp, tn, last_start >= 0);
+    uint32_t cp = __shfl_up(tp, 1, 64), cn = __shfl_up(tn, 1, 64);
+    int prev_start = __shfl_up(wave_incl_max(last_start), 1, 64);
+    int next_end = __shfl_down(wave_suffix_min(first_end), 1, 64);
+    if (lane == 0) {
+      cp = cn = 0;
+      prev_start = 0;
+    }
+    if (lane == 63) next_end = 0x7FFFFFFF;
+    // inclusive prefixes with the carry from earlier lanes; segment bounds
+    uint32_t se[C];
+    run_p = cp;
+    run_n = cn;
+    int s0 = prev_start;
+    for (int c = 0; c < C; ++c) {
+      const int t = t0 + c;
+      se[c] = 0;
+      if (t < n) {
+        if (t == 0 || L.lcn[t - 1] < k) {
+          run_p = run_n = 0;
+          s0 = t;
+        }
+        const uint32_t r = L.res[t];
+        if (L.slot[t] < nq) run_n += r;
+        else run_p += r;
+        L.pp[t] = run_p;
+        L.pn[t] = run_n;
+        se[c] = (uint32_t)s0;
+      }
+    }
+    {
+      int e = next_end;
+      for (int c = C - 1; c >= 0; --c) {
+        const int t = t0 + c;
+        if (t < n) {
+          if (L.lcn[t] < k) e = t;
+          se[c] |= (uint32_t)e << 16;
+        }
+      }
+    }
+    __syncthreads();
+    // each item finds the match that starts at its own interval start
+    uint32_t m_pos[C], m_eta[C], m_lo[C];
+    uint8_t m_bind[C];
+    int cnt = 0;
+    for (int c = 0; c < C; ++c) {
+      const int t = t0 + c;
+      m_eta[c] = 0;
+      if (t < n) {
+        const uint32_t r = L.res[t];
+        if (r > 0) {
+          const bool isq = L.slot[t] < nq;
+          const int a0 = (int)(se[c] & 0xFFFFu), e0 = (int)(se[c] >> 16);
+          const uint32_t Tp = L.pp[e0], Tn = L.pn[e0];
+          const uint32_t M = Tp < Tn ? Tp : Tn;
+          const uint32_t hi = isq ? L.pn[t] : L.pp[t];
+          const uint32_t lo = hi - r;
+          if (lo < M) {
+            const uint32_t* opp = isq ? L.pp : L.pn;
+            int a = a0, b = e0;
+            while (a < b) {
+              const int mid = (a + b) >> 1;
+              if (opp[mid] > lo) b = mid;
+              else a = mid + 1;
+            }
+            const int p = a;
+            bool own = true;
+            if (isq) {
+              const uint32_t lo_p = p == a0 ? 0u : L.pp[p - 1];
+              own = lo_p != lo;
+            }
+            if (own) {
+              const uint32_t ho = opp[p];
+              uint32_t end = hi < ho ? hi : ho;
+              end = end < M ? end : M;
+              m_eta[c] = end - lo;
+              m_pos[c] = isq ? ((uint32_t)p | ((uint32_t)t << 16)) : ((uint32_t)t | ((uint32_t)p << 16));
+              if (SAVE) {
+                const uint32_t hd = isq ? ho : hi, hq = isq ? hi : ho;
+                m_lo[c] = lo;
+                m_bind[c] = (end == hd && end == hq) ? 2 : (end == hd ? 0 : 1);
+              }
+              ++cnt;
+            }
+          }
+          L.res[t] = hi > M ? hi - (lo > M ? lo : M) : 0u;
+        }
+      }
+    }
+    const int incl = wave_incl_sum(cnt);
+    int off = E + incl - cnt;
+    const int total = __shfl(incl, 63, 64);
+    for (int c = 0; c < C; ++c) {
+      if (m_eta[c]) {
+        L.em_pos[off] = m_pos[c];
+        L.em_eta[off] = m_eta[c];
+        if (SAVE) {
+          const int64_t g = sv.base + off;
+          const uint32_t pd = m_pos[c] & 0xFFFFu, pq = m_pos[c] >> 16;
+          sv.id[g] = ((uint32_t)(L.slot[pd] - nq) << 16) | (uint32_t)L.slot[pq];
+          sv.eta[g] = m_eta[c];
+          sv.key[g] = ((uint64_t)(31 - k) << 48) | ((uint64_t)(se[c] & 0xFFFFu) << 32) | m_lo[c];
+          sv.bind[g] = m_bind[c];
+        }
+        ++off;
+      }
+    }
+    E += total;
+    __syncthreads();
+  }
+  // every unit of mass must have been matched by the root
+  bool left = false;
+  for (int c = 0; c < C; ++c)
+    if (t0 + c < n && L.res[t0 + c] != 0) left = true;
+  if (__ballot(left) && lane == 0) atomicOr(status, ERR_FLOW);
+  return E;
+}
+
+// Euclidean price of the matches: sum eta * ||x_doc - x_query||_2 (float32
+// distances, float64 accumulation).  G lanes share one match; rows are
+// read as float4 when VEC == 4.
+template <int C, int G, int VEC>
+__device__ double flow_price(const FlowLds<C>& L, const int E, const float* __restrict__ X,
+                             const uint32_t* __restrict__ row_of_rank, const int stride, const int d) {
+  const int lane = lane_id();
+  const int g = lane / G, sub = lane % G;
+  constexpr int PER = 64 / G;
+  double cost = 0.0;
+  for (int e0 = 0; e0 < E; e0 += PER) {
+    const int e = e0 + g;
+    float acc = 0.0f;
+    uint32_t eta = 0;
+    if (e < E) {
+      const uint32_t pos = L.em_pos[e];
+      const uint32_t rd = L.rank[pos & 0xFFFFu], rq = L.rank[pos >> 16];
+      eta = L.em_eta[e];
+      if (rd != rq) {
+        const int64_t rowd = row_of_rank ? row_of_rank[rd] : rd;
+        const int64_t rowq = row_of_rank ? row_of_rank[rq] : rq;
+        const float* xd = X + rowd * stride;
+        const float* xq = X + rowq * stride;
+        if (VEC == 4) {
+          const float4* a4 = reinterpret_cast<const float4*>(xd);
+          const float4* b4 = reinterpret_cast<const float4*>(xq);
+          const int nv = stride >> 2;
+          for (int v = sub; v < nv; v += G) {
+            const float4 a = a4[v], b = b4[v];
+            const float dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z, dw = a.w - b.w;
+            acc += dx * dx + dy * dy + dz * dz + dw * dw;
+          }
+        } else {
+          for (int v = sub; v < d; v += G) {
+            const float dx = xd[v] - xq[v];
+            acc += dx * dx;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (sub == 0 && e < E) cost += (double)eta * (double)sqrtf(acc);
+  }
+  return wave_sum(cost);
+}
+
+// Lanes per match from the row length in float4 units.
+inline int lanes_for(int nvec) {
+  int g = 1;
+  while (g < 16 && g < nvec) g <<= 1;
+  return g;
+}
+
+// Merged-item capacity classes: NMAX = 64 * C.
+constexpr int N_CLASSES = 5;
+constexpr int CLASS_C[N_CLASSES] = {2, 4, 8, 16, 32};
+
+inline int class_for(int n) {
+  for (int i = 0; i < N_CLASSES; ++i)
+    if (n <= 64 * CLASS_C[i]) return i;
+  return -1;
+}
+
+__device__ __forceinline__ int class_for_dev(int n) {
+  return n <= 128 ? 0 : n <= 256 ? 1 : n <= 512 ? 2 : n <= 1024 ? 3 : 4;
+}
+
+}  // namespace ft

@@ -1,0 +1,457 @@
+// Flowtree k-NN (paper Section 3; greedy of Appendix A.1): plain launches
+// (one per query) and the batched persistent schedule (all pairs, one launch
+// per pair-size class, replayed as HIP graphs, schedule picked by timing).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <fstream>
+#include <functional>
+#include <sstream>
+#include <vector>
+
+#include "common.h"
+#include "flow.h"
+#include "select.h"
+#include "wave.h"
+
+namespace ft {
+
+struct PairArgs {
+  const int64_t* q_off;
+  const uint32_t* q_rank;
+  const uint32_t* q_mass;
+  const int64_t* d_off;
+  const uint32_t* d_rank;
+  const uint32_t* d_mass;
+  const int64_t* cand;  // [n_q * n_cols] or NULL (column = doc)
+  int64_t n_cols;
+  const uint8_t* st;
+  int64_t V;
+  int B, Q;
+  const float* X;  // Morton-ordered, padded rows
+  int stride;
+  uint32_t* status;
+  float* cost;  // [n_q * n_cols]
+};
+
+template <int C, int G>
+__device__ __forceinline__ void flow_one(FlowLds<C>& L, const PairArgs& a, const int64_t p) {
+  const int64_t q = p / a.n_cols;
+  const int64_t c = p - q * a.n_cols;
+  const int64_t doc = a.cand ? a.cand[p] : c;
+  const int64_t qa = a.q_off[q], da = a.d_off[doc];
+  const int nq = (int)(a.q_off[q + 1] - qa), nd = (int)(a.d_off[doc + 1] - da);
+  if (nq + nd > FlowLds<C>::N) {  // the host sizes C; never taken
+    if (threadIdx.x == 0) atomicOr(a.status, ERR_FLOW);
+    return;
+  }
+  flow_stage(L, a.q_rank + qa, a.q_mass + qa, nq, a.d_rank + da, a.d_mass + da, nd);
+  const int E = flow_match<C, false>(L, nq, nd, a.st, a.V, a.B, FlowSave{}, a.status);
+  const double cost = flow_price<C, G, 4>(L, E, a.X, nullptr, a.stride, a.stride);
+  if (threadIdx.x == 0) a.cost[p] = (float)ldexp(cost, -a.Q);
+  __syncthreads();
+}
+
+// Plain: block b handles column b of query q.
+template <int C, int G>
+__global__ __launch_bounds__(64) void k_flow_plain(PairArgs a, int64_t q) {
+  __shared__ FlowLds<C> L;
+  flow_one<C, G>(L, a, q * a.n_cols + blockIdx.x);
+}
+
+// Persistent: waves grab chunks of the class's pair list until it is used up.
+template <int C, int G>
+__global__ __launch_bounds__(64) void k_flow_persistent(PairArgs a, const int64_t* __restrict__ list,
+                                                        const int64_t* __restrict__ offsets, int64_t n_q, int cls,
+                                                        uint32_t* __restrict__ counters, int chunk) {
+  __shared__ FlowLds<C> L;
+  const int64_t begin = offsets[(int64_t)cls * n_q], end = offsets[(int64_t)(cls + 1) * n_q];
+  while (true) {
+    uint32_t w = 0;
+    if (threadIdx.x == 0) w = atomicAdd(&counters[cls], 1u);
+    w = __shfl(w, 0, 64);
+    const int64_t i0 = begin + (int64_t)w * chunk;
+    if (i0 >= end) break;
+    const int64_t i1 = min(end, i0 + chunk);
+    for (int64_t i = i0; i < i1; ++i) flow_one<C, G>(L, a, list[i]);
+  }
+}
+
+__global__ void k_fill_u32(uint32_t* p, int n, uint32_t v) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// Per query: count candidate pairs of each size class.
+__global__ __launch_bounds__(256) void k_bucket_count(PairArgs a, int64_t n_q, int64_t* __restrict__ counts) {
+  __shared__ int64_t cnt[N_CLASSES];
+  const int64_t q = blockIdx.x;
+  if (threadIdx.x < N_CLASSES) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const int nq = (int)(a.q_off[q + 1] - a.q_off[q]);
+  for (int64_t c = threadIdx.x; c < a.n_cols; c += blockDim.x) {
+    const int64_t doc = a.cand ? a.cand[q * a.n_cols + c] : c;
+    const int n = nq + (int)(a.d_off[doc + 1] - a.d_off[doc]);
+    atomicAdd((unsigned long long*)&cnt[class_for_dev(n)], 1ull);
+  }
+  __syncthreads();
+  if (threadIdx.x < N_CLASSES) counts[(int64_t)threadIdx.x * n_q + q] = cnt[threadIdx.x];
+}
+
+// Per query (one wavefront): place its pairs into the class lists, in
+// column order.
+__global__ __launch_bounds__(64) void k_bucket_scatter(PairArgs a, int64_t n_q, const int64_t* __restrict__ offsets,
+                                                       int64_t* __restrict__ list) {
+  const int64_t q = blockIdx.x;
+  const int lane = lane_id();
+  const int nq = (int)(a.q_off[q + 1] - a.q_off[q]);
+  const int64_t per = (a.n_cols + 63) / 64;
+  const int64_t c0 = min(a.n_cols, lane * per), c1 = min(a.n_cols, c0 + per);
+  int64_t local[N_CLASSES] = {0, 0, 0, 0, 0};
+  for (int64_t c = c0; c < c1; ++c) {
+    const int64_t doc = a.cand ? a.cand[q * a.n_cols + c] : c;
+    ++local[class_for_dev(nq + (int)(a.d_off[doc + 1] - a.d_off[doc]))];
+  }
+  int64_t pos[N_CLASSES];
+#pragma unroll
+  for (int k = 0; k < N_CLASSES; ++k) pos[k] = offsets[(int64_t)k * n_q + q] + wave_incl_sum(local[k]) - local[k];
+  for (int64_t c = c0; c < c1; ++c) {
+    const int64_t doc = a.cand ? a.cand[q * a.n_cols + c] : c;
+    const int k = class_for_dev(nq + (int)(a.d_off[doc + 1] - a.d_off[doc]));
+    list[pos[k]++] = q * a.n_cols + c;
+  }
+}
+
+// ------------------------------------------------------------ dispatch --
+
+template <int C>
+static void launch_plain_c(int G, const PairArgs& a, int64_t q, hipStream_t s) {
+  dim3 grid((unsigned)a.n_cols);
+  switch (G) {
+    case 1: k_flow_plain<C, 1><<<grid, 64, 0, s>>>(a, q); break;
+    case 2: k_flow_plain<C, 2><<<grid, 64, 0, s>>>(a, q); break;
+    case 4: k_flow_plain<C, 4><<<grid, 64, 0, s>>>(a, q); break;
+    case 8: k_flow_plain<C, 8><<<grid, 64, 0, s>>>(a, q); break;
+    default: k_flow_plain<C, 16><<<grid, 64, 0, s>>>(a, q); break;
+  }
+}
+
+static void launch_plain(int cls, int G, const PairArgs& a, int64_t q, hipStream_t s) {
+  switch (cls) {
+    case 0: launch_plain_c<2>(G, a, q, s); break;
+    case 1: launch_plain_c<4>(G, a, q, s); break;
+    case 2: launch_plain_c<8>(G, a, q, s); break;
+    case 3: launch_plain_c<16>(G, a, q, s); break;
+    default: launch_plain_c<32>(G, a, q, s); break;
+  }
+}
+
+template <int C, int G>
+static const void* persistent_fn() {
+  return reinterpret_cast<const void*>(&k_flow_persistent<C, G>);
+}
+
+static const void* persistent_kernel(int cls, int G) {
+#define FT_PK(CC)                                   \
+  switch (G) {                                      \
+    case 1: return persistent_fn<CC, 1>();          \
+    case 2: return persistent_fn<CC, 2>();          \
+    case 4: return persistent_fn<CC, 4>();          \
+    case 8: return persistent_fn<CC, 8>();          \
+    default: return persistent_fn<CC, 16>();        \
+  }
+  switch (cls) {
+    case 0: FT_PK(2)
+    case 1: FT_PK(4)
+    case 2: FT_PK(8)
+    case 3: FT_PK(16)
+    default: FT_PK(32)
+  }
+#undef FT_PK
+}
+
+template <int C>
+static void launch_persistent_c(int G, unsigned blocks, const PairArgs& a, const int64_t* list, const int64_t* offsets,
+                                int64_t n_q, int cls, uint32_t* counters, int chunk, hipStream_t s) {
+  switch (G) {
+    case 1: k_flow_persistent<C, 1><<<blocks, 64, 0, s>>>(a, list, offsets, n_q, cls, counters, chunk); break;
+    case 2: k_flow_persistent<C, 2><<<blocks, 64, 0, s>>>(a, list, offsets, n_q, cls, counters, chunk); break;
+    case 4: k_flow_persistent<C, 4><<<blocks, 64, 0, s>>>(a, list, offsets, n_q, cls, counters, chunk); break;
+    case 8: k_flow_persistent<C, 8><<<blocks, 64, 0, s>>>(a, list, offsets, n_q, cls, counters, chunk); break;
+    default: k_flow_persistent<C, 16><<<blocks, 64, 0, s>>>(a, list, offsets, n_q, cls, counters, chunk); break;
+  }
+}
+
+static void launch_persistent(int cls, int G, unsigned blocks, const PairArgs& a, const int64_t* list,
+                              const int64_t* offsets, int64_t n_q, uint32_t* counters, int chunk, hipStream_t s) {
+  switch (cls) {
+    case 0: launch_persistent_c<2>(G, blocks, a, list, offsets, n_q, cls, counters, chunk, s); break;
+    case 1: launch_persistent_c<4>(G, blocks, a, list, offsets, n_q, cls, counters, chunk, s); break;
+    case 2: launch_persistent_c<8>(G, blocks, a, list, offsets, n_q, cls, counters, chunk, s); break;
+    case 3: launch_persistent_c<16>(G, blocks, a, list, offsets, n_q, cls, counters, chunk, s); break;
+    default: launch_persistent_c<32>(G, blocks, a, list, offsets, n_q, cls, counters, chunk, s); break;
+  }
+}
+
+// ------------------------------------------------------------- batched --
+
+struct BatchedPlan {
+  int G = 16;
+  int64_t n_q = 0, n_cols = 0;
+  int64_t* counts = nullptr;   // [N_CLASSES * n_q]
+  int64_t* offsets = nullptr;  // [N_CLASSES * n_q + 1]
+  int64_t* scan_tmp = nullptr;
+  int64_t* list = nullptr;     // [n_q * n_cols]
+  uint32_t* counters = nullptr;
+  unsigned blocks[N_CLASSES] = {0, 0, 0, 0, 0};
+  int chunk = 4;
+};
+
+static void enqueue_bucketing(const PairArgs& a, const BatchedPlan& P, hipStream_t s) {
+  k_fill_u32<<<1, 64, 0, s>>>(P.counters, N_CLASSES, 0u);
+  k_bucket_count<<<(unsigned)P.n_q, 256, 0, s>>>(a, P.n_q, P.counts);
+  exclusive_scan_i64(P.counts, P.offsets, (int64_t)N_CLASSES * P.n_q, P.scan_tmp, s);
+  k_bucket_scatter<<<(unsigned)P.n_q, 64, 0, s>>>(a, P.n_q, P.offsets, P.list);
+  FT_HIP(hipGetLastError());
+}
+
+static void enqueue_persistent(const PairArgs& a, const BatchedPlan& P, hipStream_t s) {
+  for (int cls = 0; cls < N_CLASSES; ++cls)
+    if (P.blocks[cls]) launch_persistent(cls, P.G, P.blocks[cls], a, P.list, P.offsets, P.n_q, P.counters, P.chunk, s);
+  FT_HIP(hipGetLastError());
+}
+
+static unsigned occupancy_blocks(ft_index* ix, int cls, int G) {
+  int per_cu = 0;
+  FT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel(cls, G), 64, 0));
+  per_cu = std::max(1, per_cu);
+  return (unsigned)(per_cu * ix->n_cu);
+}
+
+static hipGraphExec_t capture(ft_index* ix, const std::function<void(hipStream_t)>& body) {
+  hipGraph_t g = nullptr;
+  hipGraphExec_t e = nullptr;
+  FT_HIP(hipStreamBeginCapture(ix->work, hipStreamCaptureModeThreadLocal));
+  try {
+    body(ix->work);
+  } catch (...) {
+    (void)hipStreamEndCapture(ix->work, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  FT_HIP(hipStreamEndCapture(ix->work, &g));
+  hipError_t err = hipGraphInstantiate(&e, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  FT_HIP(err);
+  return e;
+}
+
+static std::string tune_signature(const ft_index* ix, int64_t n_q, int64_t n_cols, bool all_docs) {
+  std::ostringstream o;
+  o << "gfx950/V" << ix->V << "/d" << ix->d << "/docs" << ix->docs.n << "/maxd" << ix->docs.max_size << "/nq" << n_q
+    << "/cols" << n_cols << (all_docs ? "/all" : "/cand");
+  return o.str();
+}
+
+static void load_tune_cache(ft_index* ix) {
+  const char* path = getenv("FT_TUNE_CACHE");
+  if (!path) return;
+  std::ifstream f(path);
+  std::string line;
+  while (std::getline(f, line)) {
+    // one entry per line: "signature chunk occupancy_percent"
+    std::istringstream ls(line);
+    std::string sig;
+    TuneChoice c;
+    if (ls >> sig >> c.chunk >> c.blocks_per_cu) ix->tuned[sig] = c;
+  }
+}
+
+static void save_tune_cache(const ft_index* ix) {
+  const char* path = getenv("FT_TUNE_CACHE");
+  if (!path) return;
+  std::ofstream f(path);
+  for (auto& kv : ix->tuned) f << kv.first << " " << kv.second.chunk << " " << kv.second.blocks_per_cu << "\n";
+}
+
+static void set_blocks(ft_index* ix, BatchedPlan& P, int occupancy_percent) {
+  for (int cls = 0; cls < N_CLASSES; ++cls) {
+    unsigned full = occupancy_blocks(ix, cls, P.G);
+    P.blocks[cls] = std::max(1u, (unsigned)((uint64_t)full * occupancy_percent / 100));
+  }
+}
+
+}  // namespace ft
+
+using namespace ft;
+
+static void flowtree_plain(ft_index* ix, const PairArgs& a, int64_t n_q, hipStream_t s) {
+  std::vector<int64_t> qoff(n_q + 1);
+  FT_HIP(hipMemcpyAsync(qoff.data(), a.q_off, (n_q + 1) * 8, hipMemcpyDeviceToHost, s));
+  FT_HIP(hipStreamSynchronize(s));
+  const int G = lanes_for(ix->dp / 4);
+  for (int64_t q = 0; q < n_q; ++q) {
+    const int cls = class_for((int)(qoff[q + 1] - qoff[q]) + ix->docs.max_size);
+    FT_REQUIRE(cls >= 0, FT_ERANGE, "pair larger than 2048 items");
+    launch_plain(cls, G, a, q, s);
+  }
+  FT_HIP(hipGetLastError());
+}
+
+static void flowtree_batched(ft_index* ix, const PairArgs& a, int64_t n_q, hipStream_t s) {
+  const int64_t n_cols = a.n_cols;
+  const int64_t npairs = n_q * n_cols;
+  BatchedPlan P;
+  P.G = lanes_for(ix->dp / 4);
+  P.n_q = n_q;
+  P.n_cols = n_cols;
+  const int64_t nc = (int64_t)N_CLASSES * n_q;
+  int64_t* misc = (int64_t*)ix->ws_counts.ensure((nc + nc + 1 + scan_tmp_elems(nc) + 8) * 8);
+  P.counts = misc;
+  P.offsets = misc + nc;
+  P.scan_tmp = misc + 2 * nc + 1;
+  P.counters = (uint32_t*)(misc + 2 * nc + 1 + scan_tmp_elems(nc));
+  P.list = (int64_t*)ix->ws_lists.ensure(npairs * 8);
+
+  // schedule: tuned on first use of a shape
+  if (ix->tuned.empty()) load_tune_cache(ix);
+  const std::string sig = tune_signature(ix, n_q, n_cols, a.cand == nullptr);
+  auto it = ix->tuned.find(sig);
+  TuneChoice choice;
+  if (it != ix->tuned.end()) {
+    choice = it->second;
+  } else if (ix->autotune > 0) {
+    // time the persistent launches for each candidate schedule
+    enqueue_bucketing(a, P, s);
+    float best = 1e30f;
+    for (int occ : {100, 50}) {
+      for (int chunk : {1, 2, 4, 8, 16}) {
+        P.chunk = chunk;
+        set_blocks(ix, P, occ);
+        float ms = 0.0f;
+        for (int rep = 0; rep < 2; ++rep) {
+          k_fill_u32<<<1, 64, 0, s>>>(P.counters, N_CLASSES, 0u);
+          FT_HIP(hipEventRecord(ix->ev_t0, s));
+          enqueue_persistent(a, P, s);
+          FT_HIP(hipEventRecord(ix->ev_t1, s));
+          FT_HIP(hipEventSynchronize(ix->ev_t1));
+          FT_HIP(hipEventElapsedTime(&ms, ix->ev_t0, ix->ev_t1));
+        }
+        if (ms < best) {
+          best = ms;
+          choice.chunk = chunk;
+          choice.blocks_per_cu = occ;
+        }
+      }
+    }
+    ix->tuned[sig] = choice;
+    save_tune_cache(ix);
+  } else {
+    choice.chunk = 4;
+    choice.blocks_per_cu = 100;
+  }
+  P.chunk = choice.chunk;
+  set_blocks(ix, P, choice.blocks_per_cu > 0 ? choice.blocks_per_cu : 100);
+  {
+    std::ostringstream o;
+    o << "chunk=" << P.chunk << " occupancy=" << (choice.blocks_per_cu > 0 ? choice.blocks_per_cu : 100)
+      << "% blocks=";
+    for (int cls = 0; cls < N_CLASSES; ++cls) o << (cls ? "," : "") << P.blocks[cls];
+    o << " lanes_per_match=" << P.G;
+    ix->last_schedule = o.str();
+  }
+
+  // two graphs, bucketing and the persistent Flowtree launches; events
+  // between them time the persistent launches
+  BatchedGraphs& BG = ix->graphs;
+  std::vector<uint64_t> key = {(uint64_t)a.q_off,   (uint64_t)a.q_rank,  (uint64_t)a.q_mass, (uint64_t)a.cand,
+                               (uint64_t)n_cols,    (uint64_t)n_q,       (uint64_t)a.cost,   (uint64_t)P.list,
+                               (uint64_t)P.counts,  (uint64_t)P.chunk,   (uint64_t)P.blocks[0], (uint64_t)P.blocks[4],
+                               (uint64_t)a.status};
+  if (BG.key != key) {
+    BG.reset();
+    BG.pre = capture(ix, [&](hipStream_t w) { enqueue_bucketing(a, P, w); });
+    BG.main = capture(ix, [&](hipStream_t w) { enqueue_persistent(a, P, w); });
+    BG.key = key;
+  }
+  FT_HIP(hipEventRecord(ix->ev_a, s));
+  FT_HIP(hipStreamWaitEvent(ix->work, ix->ev_a, 0));
+  FT_HIP(hipGraphLaunch(BG.pre, ix->work));
+  FT_HIP(hipEventRecord(ix->ev_t0, ix->work));
+  FT_HIP(hipGraphLaunch(BG.main, ix->work));
+  FT_HIP(hipEventRecord(ix->ev_t1, ix->work));
+  FT_HIP(hipEventRecord(ix->ev_b, ix->work));
+  FT_HIP(hipStreamWaitEvent(s, ix->ev_b, 0));
+}
+
+extern "C" ft_status ft_flowtree_knn(ft_index* ix, const int64_t* q_off, const uint32_t* q_id, const uint32_t* q_mass,
+                                     int64_t n_q, const int64_t* cand, int32_t n_cand, int32_t k, int32_t mode,
+                                     float* out_cost, int64_t* out_doc, void* stream) {
+  return guarded([&] {
+    FT_REQUIRE(ix && out_cost && out_doc, FT_EINVAL, "NULL argument");
+    FT_REQUIRE(mode == FT_PLAIN || mode == FT_BATCHED, FT_EINVAL, "mode must be FT_PLAIN or FT_BATCHED");
+    std::lock_guard<std::mutex> lock(ix->mu);
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n_cols = cand ? (int64_t)n_cand : ix->docs.n;
+    FT_REQUIRE(!cand || (n_cand >= 1 && n_cand <= 4096), FT_ERANGE, "n_cand must lie in [1, 4096]");
+    FT_REQUIRE(k >= 1 && k <= n_cols, FT_EINVAL, "k must lie in [1, number of candidates]");
+    FT_REQUIRE(cand || n_cols <= 4096 || k <= 1024, FT_ERANGE, "k > 1024 needs at most 4096 candidates");
+    prepare_dists(ix, ix->qry, q_off, q_id, q_mass, n_q, false, s, "queries");
+    if (cand) check_indices(ix, cand, n_q * n_cand, ix->docs.n, s, "cand");
+    FT_REQUIRE(class_for(ix->qry.max_size + ix->docs.max_size) >= 0, FT_ERANGE, "pair larger than 2048 items");
+    // queries in chunks so the cost buffer stays near 1 GiB
+    const int64_t rows = std::max<int64_t>(1, std::min<int64_t>(n_q, (int64_t(1) << 28) / n_cols));
+    float* cost = (float*)ix->ws_cost.ensure(rows * n_cols * 4);
+    for (int64_t r0 = 0; r0 < n_q; r0 += rows) {
+      const int64_t r1 = std::min(n_q, r0 + rows);
+      PairArgs a;
+      a.q_off = ix->qry.off.as<int64_t>() + r0;
+      a.q_rank = ix->qry.rank.as<uint32_t>();
+      a.q_mass = ix->qry.mass.as<uint32_t>();
+      a.d_off = ix->docs.off.as<int64_t>();
+      a.d_rank = ix->docs.rank.as<uint32_t>();
+      a.d_mass = ix->docs.mass.as<uint32_t>();
+      a.cand = cand ? cand + r0 * n_cols : nullptr;
+      a.n_cols = n_cols;
+      a.st = ix->st.as<uint8_t>();
+      a.V = ix->V;
+      a.B = ix->B;
+      a.Q = ix->Q;
+      a.X = ix->Xm.as<float>();
+      a.stride = ix->dp;
+      a.status = ix->status.as<uint32_t>();
+      a.cost = cost;
+      if (mode == FT_PLAIN) flowtree_plain(ix, a, r1 - r0, s);
+      else flowtree_batched(ix, a, r1 - r0, s);
+      topk_rows(cost, r1 - r0, n_cols, a.cand, k, out_cost + r0 * k, out_doc + r0 * k, s);
+    }
+    uint32_t flags = read_and_clear_status(ix, s);
+    FT_REQUIRE(flags == 0, FT_EHIP, "flowtree kernel reported:" + describe_flags(flags));
+    if (mode == FT_BATCHED) {
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, ix->ev_t0, ix->ev_t1) == hipSuccess) ix->last_batched_ms = ms;
+    }
+  });
+}
+
+extern "C" ft_status ft_set_autotune(ft_index* ix, int32_t level) {
+  return guarded([&] {
+    FT_REQUIRE(ix, FT_EINVAL, "NULL index");
+    FT_REQUIRE(level == 0 || level == 1, FT_EINVAL, "level must be 0 or 1");
+    ix->autotune = level;
+  });
+}
+
+extern "C" ft_status ft_last_batched_stats(const ft_index* ix, double* ms, char* schedule, int32_t len) {
+  return guarded([&] {
+    FT_REQUIRE(ix, FT_EINVAL, "NULL index");
+    if (ms) *ms = ix->last_batched_ms;
+    if (schedule && len > 0) {
+      std::snprintf(schedule, (size_t)len, "%s", ix->last_schedule.c_str());
+    }
+  });
+}
+

@@ -1,0 +1,411 @@
+// Flowtree of explicit pairs with the flow kept: inspection of the flow, and
+// the cost's gradient with the tree and the flow pattern frozen.
+//
+// The paper defines no gradient.  With the pattern frozen, each match moves
+// the unmatched mass of the item it used up (the doc item when both were used
+// up), so every moved mass is a linear function of the weights w = mass/2^Q:
+//   eta_e = r(bind_e);  r(doc_e) -= eta_e;  r(query_e) -= eta_e,
+// and C = sum_e eta_e * D_e with D_e = ||x_doc - x_query||_2.  Then
+//   dC/dx = eta_e (x_doc - x_query) / D_e on the doc point (minus on the query
+//           point), 0 when D_e = 0;
+//   dC/dw by reverse accumulation in the greedy's own order:
+//           lambda_e = D_e - acc[doc_e] - acc[query_e];  acc[bind_e] += lambda_e
+//           for e from the last match to the first; dC/dw_i = acc[i].
+// The greedy's order is deepest cells first, and inside a cell increasing
+// position of the match along the cumulative-mass axis; every saved match
+// carries that order as a sort key.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "common.h"
+#include "flow.h"
+#include "wave.h"
+
+namespace ft {
+
+struct SaveArgs {
+  const int64_t* pair_q;
+  const int64_t* pair_d;
+  const int64_t* base;  // first saved entry of each pair
+  const int64_t* q_off;
+  const uint32_t* q_rank;
+  const uint32_t* q_mass;
+  const int64_t* d_off;
+  const uint32_t* d_rank;
+  const uint32_t* d_mass;
+  const uint8_t* st;
+  int64_t V;
+  int B, Q;
+  const float* X;  // caller's coordinates, original order
+  const uint32_t* perm;
+  int d;
+  uint32_t* status;
+  FlowSave sv;
+  int32_t* count;
+  float* cost;  // NULL: do not price
+};
+
+template <int C, int G, int VEC>
+__global__ __launch_bounds__(64) void k_flow_save(SaveArgs a) {
+  __shared__ FlowLds<C> L;
+  const int64_t p = blockIdx.x;
+  const int64_t q = a.pair_q[p], doc = a.pair_d[p];
+  const int64_t qa = a.q_off[q], da = a.d_off[doc];
+  const int nq = (int)(a.q_off[q + 1] - qa), nd = (int)(a.d_off[doc + 1] - da);
+  if (nq + nd > FlowLds<C>::N) {
+    if (threadIdx.x == 0) atomicOr(a.status, ERR_FLOW);
+    return;
+  }
+  flow_stage(L, a.q_rank + qa, a.q_mass + qa, nq, a.d_rank + da, a.d_mass + da, nd);
+  FlowSave sv = a.sv;
+  sv.base = a.base[p];
+  const int E = flow_match<C, true>(L, nq, nd, a.st, a.V, a.B, sv, a.status);
+  if (threadIdx.x == 0) a.count[p] = E;
+  if (a.cost) {
+    const double c = flow_price<C, G, VEC>(L, E, a.X, a.perm, a.d, a.d);
+    if (threadIdx.x == 0) a.cost[p] = (float)ldexp(c, -a.Q);
+  }
+}
+
+__global__ void k_pair_sizes(const int64_t* __restrict__ pair_q, const int64_t* __restrict__ pair_d, int64_t n,
+                             const int64_t* __restrict__ q_off, const int64_t* __restrict__ d_off,
+                             int64_t* __restrict__ out) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  out[p] = (q_off[pair_q[p] + 1] - q_off[pair_q[p]]) + (d_off[pair_d[p] + 1] - d_off[pair_d[p]]);
+}
+
+// Saved flow -> caller arrays of original point ids.
+__global__ void k_flows_out(const int64_t* __restrict__ pair_q, const int64_t* __restrict__ pair_d, int64_t n,
+                            const int64_t* __restrict__ base, const int32_t* __restrict__ cnt,
+                            const int64_t* __restrict__ cap_off, const uint32_t* __restrict__ id,
+                            const uint32_t* __restrict__ eta, const uint8_t* __restrict__ bind,
+                            const int64_t* __restrict__ q_off, const uint32_t* __restrict__ q_rank,
+                            const int64_t* __restrict__ d_off, const uint32_t* __restrict__ d_rank,
+                            const uint32_t* __restrict__ perm, int32_t* __restrict__ count,
+                            uint32_t* __restrict__ fd, uint32_t* __restrict__ fq, uint32_t* __restrict__ fe,
+                            uint8_t* __restrict__ fb, uint32_t* __restrict__ status) {
+  const int64_t p = blockIdx.x;
+  if (p >= n) return;
+  const int E = cnt[p];
+  const int64_t o = cap_off[p];
+  if (cap_off[p + 1] - o < E) {
+    if (threadIdx.x == 0) atomicOr(status, ERR_SIZE);
+    return;
+  }
+  const int64_t qa = q_off[pair_q[p]], da = d_off[pair_d[p]];
+  for (int e = threadIdx.x; e < E; e += blockDim.x) {
+    const uint32_t v = id[base[p] + e];
+    fd[o + e] = perm[d_rank[da + (v >> 16)]];
+    fq[o + e] = perm[q_rank[qa + (v & 0xFFFFu)]];
+    fe[o + e] = eta[base[p] + e];
+    fb[o + e] = bind[base[p] + e];
+  }
+  if (threadIdx.x == 0) count[p] = E;
+}
+
+// Backward of one pair on one wavefront.
+template <int C, int G, int VEC>
+__global__ __launch_bounds__(64) void k_flow_bwd(const int64_t* __restrict__ pair_q, const int64_t* __restrict__ pair_d,
+                                                 const int64_t* __restrict__ base, const int32_t* __restrict__ cnt,
+                                                 const uint32_t* __restrict__ fid, const uint32_t* __restrict__ feta,
+                                                 const uint64_t* __restrict__ fkey, const uint8_t* __restrict__ fbind,
+                                                 const int64_t* __restrict__ q_off, const uint32_t* __restrict__ q_rank,
+                                                 const uint16_t* __restrict__ q_pos, const int64_t* __restrict__ d_off,
+                                                 const uint32_t* __restrict__ d_rank,
+                                                 const uint16_t* __restrict__ d_pos, const uint32_t* __restrict__ perm,
+                                                 const float* __restrict__ X, int d, int Q,
+                                                 const float* __restrict__ grad_out, float* __restrict__ gX,
+                                                 float* __restrict__ gq, float* __restrict__ gd) {
+  constexpr int N = 64 * C;
+  __shared__ uint64_t skey[N];
+  __shared__ uint16_t sidx[N];
+  __shared__ float sD[N];
+  __shared__ double acc[N];
+  const int64_t p = blockIdx.x;
+  const float g = grad_out[p];
+  const int E = cnt[p];
+  const int64_t b0 = base[p];
+  const int64_t qa = q_off[pair_q[p]], da = d_off[pair_d[p]];
+  const int nq = (int)(q_off[pair_q[p] + 1] - qa), nd = (int)(d_off[pair_d[p] + 1] - da);
+  const int lane = lane_id();
+  int P = 1;
+  while (P < E) P <<= 1;
+  for (int e = lane; e < P; e += 64) {
+    skey[e] = e < E ? fkey[b0 + e] : ~0ull;
+    sidx[e] = (uint16_t)e;
+  }
+  for (int i = lane; i < nq + nd; i += 64) acc[i] = 0.0;
+  __syncthreads();
+  // the greedy's order
+  for (int k = 2; k <= P; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int t = lane; t < P; t += 64) {
+        const int l = t ^ j;
+        if (l > t) {
+          const uint64_t x = skey[t], y = skey[l];
+          const bool up = (t & k) == 0;
+          if (up ? (y < x) : (x < y)) {
+            skey[t] = y;
+            skey[l] = x;
+            const uint16_t u = sidx[t];
+            sidx[t] = sidx[l];
+            sidx[l] = u;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  // distances and coordinate gradients: G lanes per match
+  const int grp = lane / G, sub = lane % G;
+  constexpr int PER = 64 / G;
+  const double wscale = ldexp(1.0, -Q);
+  for (int r0 = 0; r0 < E; r0 += PER) {
+    const int r = r0 + grp;
+    float dd = 0.0f;
+    const float* xd = nullptr;
+    const float* xq = nullptr;
+    float* gxd = nullptr;
+    float* gxq = nullptr;
+    uint32_t eta = 0;
+    if (r < E) {
+      const int e = sidx[r];
+      const uint32_t v = fid[b0 + e];
+      eta = feta[b0 + e];
+      const int64_t rowd = perm[d_rank[da + (v >> 16)]], rowq = perm[q_rank[qa + (v & 0xFFFFu)]];
+      if (rowd != rowq) {
+        xd = X + rowd * d;
+        xq = X + rowq * d;
+        gxd = gX ? gX + rowd * d : nullptr;
+        gxq = gX ? gX + rowq * d : nullptr;
+        if (VEC == 4) {
+          for (int i = sub; i < d / 4; i += G) {
+            const float4 a4 = reinterpret_cast<const float4*>(xd)[i], b4 = reinterpret_cast<const float4*>(xq)[i];
+            const float dx = a4.x - b4.x, dy = a4.y - b4.y, dz = a4.z - b4.z, dw = a4.w - b4.w;
+            dd += dx * dx + dy * dy + dz * dz + dw * dw;
+          }
+        } else {
+          for (int i = sub; i < d; i += G) {
+            const float dx = xd[i] - xq[i];
+            dd += dx * dx;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) dd += __shfl_xor(dd, o, 64);
+    const float D = sqrtf(dd);
+    if (r < E && sub == 0) sD[r] = D;
+    if (r < E && xd && D > 0.0f && gxd) {
+      const float coef = (float)((double)g * (double)eta * wscale / (double)D);
+      for (int i = sub; i < d; i += G) {
+        const float diff = (xd[i] - xq[i]) * coef;
+        atomicAdd(gxd + i, diff);
+        atomicAdd(gxq + i, -diff);
+      }
+    }
+  }
+  __syncthreads();
+  // weight adjoints: reverse sweep in the greedy's order (one lane)
+  if (lane == 0) {
+    for (int r = E - 1; r >= 0; --r) {
+      const int e = sidx[r];
+      const uint32_t v = fid[b0 + e];
+      const int sd = nq + (int)(v >> 16), sq = (int)(v & 0xFFFFu);
+      const double lam = (double)sD[r] - acc[sd] - acc[sq];
+      if (fbind[b0 + e] == 1) acc[sq] += lam;
+      else acc[sd] += lam;
+    }
+  }
+  __syncthreads();
+  for (int i = lane; i < nq; i += 64)
+    if (gq) atomicAdd(gq + qa + q_pos[qa + i], (float)((double)g * acc[i]));
+  for (int i = lane; i < nd; i += 64)
+    if (gd) atomicAdd(gd + da + d_pos[da + i], (float)((double)g * acc[nq + i]));
+}
+
+// Copies of the FT_FWD arguments, compared element by element in FT_BWD.
+__global__ void k_copy_or_compare(const uint8_t* __restrict__ a, uint8_t* __restrict__ keep, int64_t n, int compare,
+                                  uint32_t* __restrict__ status) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (compare) {
+    if (a[i] != keep[i]) atomicOr(status, ERR_EMPTY);
+  } else {
+    keep[i] = a[i];
+  }
+}
+
+// ------------------------------------------------------------- dispatch --
+
+#define FT_DISPATCH_CG(KERNEL, cls, G, VEC, grid, s, ...)                                    \
+  do {                                                                                       \
+    auto go = [&](auto cc, auto gg, auto vv) {                                              \
+      KERNEL<decltype(cc)::value, decltype(gg)::value, decltype(vv)::value><<<grid, 64, 0, s>>>(__VA_ARGS__); \
+    };                                                                                       \
+    auto gsel = [&](auto cc, auto vv) {                                                      \
+      switch (G) {                                                                           \
+        case 1: go(cc, std::integral_constant<int, 1>{}, vv); break;                         \
+        case 2: go(cc, std::integral_constant<int, 2>{}, vv); break;                         \
+        case 4: go(cc, std::integral_constant<int, 4>{}, vv); break;                         \
+        case 8: go(cc, std::integral_constant<int, 8>{}, vv); break;                         \
+        default: go(cc, std::integral_constant<int, 16>{}, vv); break;                       \
+      }                                                                                      \
+    };                                                                                       \
+    auto vsel = [&](auto cc) {                                                               \
+      if (VEC == 4) gsel(cc, std::integral_constant<int, 4>{});                              \
+      else gsel(cc, std::integral_constant<int, 1>{});                                       \
+    };                                                                                       \
+    switch (cls) {                                                                           \
+      case 0: vsel(std::integral_constant<int, 2>{}); break;                                 \
+      case 1: vsel(std::integral_constant<int, 4>{}); break;                                 \
+      case 2: vsel(std::integral_constant<int, 8>{}); break;                                 \
+      case 3: vsel(std::integral_constant<int, 16>{}); break;                                \
+      default: vsel(std::integral_constant<int, 32>{}); break;                               \
+    }                                                                                        \
+  } while (0)
+
+// Prepare queries, validate pairs, compute per-pair saved-entry offsets and run
+// the saving kernel.  Returns the class used.
+static int run_save(ft_index* ix, const float* X, const int64_t* q_off, const uint32_t* q_id, const uint32_t* q_mass,
+                    int64_t n_q, const int64_t* pair_q, const int64_t* pair_d, int64_t n_pairs, float* cost,
+                    hipStream_t s) {
+  prepare_dists(ix, ix->qry, q_off, q_id, q_mass, n_q, false, s, "queries");
+  check_indices(ix, pair_q, n_pairs, n_q, s, "pair_q");
+  check_indices(ix, pair_d, n_pairs, ix->docs.n, s, "pair_d");
+  const int cls = class_for(ix->qry.max_size + ix->docs.max_size);
+  FT_REQUIRE(cls >= 0, FT_ERANGE, "pair larger than 2048 items");
+  int64_t* sizes = (int64_t*)ix->ws_misc.ensure((n_pairs + scan_tmp_elems(n_pairs)) * 8);
+  int64_t* base = (int64_t*)ix->fwd_base.ensure((n_pairs + 1) * 8);
+  k_pair_sizes<<<(unsigned)ceil_div(n_pairs, 256), 256, 0, s>>>(pair_q, pair_d, n_pairs, ix->qry.off.as<int64_t>(),
+                                                                ix->docs.off.as<int64_t>(), sizes);
+  exclusive_scan_i64(sizes, base, n_pairs, sizes + n_pairs, s);
+  int64_t total = 0;
+  FT_HIP(hipMemcpyAsync(&total, base + n_pairs, 8, hipMemcpyDeviceToHost, s));
+  FT_HIP(hipStreamSynchronize(s));
+  SaveArgs a;
+  a.pair_q = pair_q;
+  a.pair_d = pair_d;
+  a.base = base;
+  a.q_off = ix->qry.off.as<int64_t>();
+  a.q_rank = ix->qry.rank.as<uint32_t>();
+  a.q_mass = ix->qry.mass.as<uint32_t>();
+  a.d_off = ix->docs.off.as<int64_t>();
+  a.d_rank = ix->docs.rank.as<uint32_t>();
+  a.d_mass = ix->docs.mass.as<uint32_t>();
+  a.st = ix->st.as<uint8_t>();
+  a.V = ix->V;
+  a.B = ix->B;
+  a.Q = ix->Q;
+  a.X = X;
+  a.perm = ix->perm.as<uint32_t>();
+  a.d = ix->d;
+  a.status = ix->status.as<uint32_t>();
+  a.sv.id = (uint32_t*)ix->fwd_id.ensure(std::max<int64_t>(total, 1) * 4);
+  a.sv.eta = (uint32_t*)ix->fwd_eta.ensure(std::max<int64_t>(total, 1) * 4);
+  a.sv.key = (uint64_t*)ix->fwd_key.ensure(std::max<int64_t>(total, 1) * 8);
+  a.sv.bind = (uint8_t*)ix->fwd_bind.ensure(std::max<int64_t>(total, 1));
+  a.sv.base = 0;
+  a.count = (int32_t*)ix->fwd_cnt.ensure(n_pairs * 4);
+  a.cost = cost;
+  const int G = lanes_for((ix->d + 3) / 4);
+  const int VEC = (X && ix->d % 4 == 0 && ((uintptr_t)X & 15) == 0) ? 4 : 1;
+  FT_DISPATCH_CG(k_flow_save, cls, G, VEC, dim3((unsigned)n_pairs), s, a);
+  FT_HIP(hipGetLastError());
+  ix->fwd_pairs = n_pairs;
+  ix->fwd_cap = total;
+  return cls;
+}
+
+}  // namespace ft
+
+using namespace ft;
+
+extern "C" ft_status ft_flowtree_flows(ft_index* ix, const int64_t* q_off, const uint32_t* q_id,
+                                       const uint32_t* q_mass, int64_t n_q, const int64_t* pair_q,
+                                       const int64_t* pair_d, int64_t n_pairs, const int64_t* cap_off, int32_t* count,
+                                       uint32_t* flow_d, uint32_t* flow_q, uint32_t* flow_eta, uint8_t* flow_bind,
+                                       void* stream) {
+  return guarded([&] {
+    FT_REQUIRE(ix && pair_q && pair_d && cap_off && count && flow_d && flow_q && flow_eta && flow_bind, FT_EINVAL,
+               "NULL argument");
+    FT_REQUIRE(n_pairs >= 1, FT_EINVAL, "need at least one pair");
+    std::lock_guard<std::mutex> lock(ix->mu);
+    hipStream_t s = (hipStream_t)stream;
+    run_save(ix, nullptr, q_off, q_id, q_mass, n_q, pair_q, pair_d, n_pairs, nullptr, s);
+    ix->fwd_valid = false;  // the saved flow no longer matches any FT_FWD call
+    k_flows_out<<<(unsigned)n_pairs, 64, 0, s>>>(
+        pair_q, pair_d, n_pairs, ix->fwd_base.as<int64_t>(), ix->fwd_cnt.as<int32_t>(), cap_off,
+        ix->fwd_id.as<uint32_t>(), ix->fwd_eta.as<uint32_t>(), ix->fwd_bind.as<uint8_t>(), ix->qry.off.as<int64_t>(),
+        ix->qry.rank.as<uint32_t>(), ix->docs.off.as<int64_t>(), ix->docs.rank.as<uint32_t>(),
+        ix->perm.as<uint32_t>(), count, flow_d, flow_q, flow_eta, flow_bind, ix->status.as<uint32_t>());
+    FT_HIP(hipGetLastError());
+    uint32_t flags = read_and_clear_status(ix, s);
+    if (flags & ERR_SIZE) throw Error(FT_EINVAL, "cap_off leaves a pair too few slots");
+    FT_REQUIRE(flags == 0, FT_EHIP, "flowtree kernel reported:" + describe_flags(flags));
+  });
+}
+
+extern "C" ft_status ft_flowtree_cost_grad(ft_index* ix, const float* X, const int64_t* q_off, const uint32_t* q_id,
+                                           const uint32_t* q_mass, int64_t n_q, const int64_t* pair_q,
+                                           const int64_t* pair_d, int64_t n_pairs, int32_t mode,
+                                           const float* grad_out, float* cost, float* grad_X, float* grad_qmass,
+                                           float* grad_dmass, void* stream) {
+  return guarded([&] {
+    FT_REQUIRE(ix && X && pair_q && pair_d, FT_EINVAL, "NULL argument");
+    FT_REQUIRE(n_pairs >= 1, FT_EINVAL, "need at least one pair");
+    FT_REQUIRE(mode == FT_FWD || mode == FT_BWD, FT_EINVAL, "mode must be FT_FWD or FT_BWD");
+    std::lock_guard<std::mutex> lock(ix->mu);
+    hipStream_t s = (hipStream_t)stream;
+    // byte images of the arguments that define the saved flows
+    auto keep_args = [&](int compare) {
+      int64_t nnz = 0;
+      FT_HIP(hipMemcpyAsync(&nnz, q_off + n_q, 8, hipMemcpyDeviceToHost, s));
+      FT_HIP(hipStreamSynchronize(s));
+      const int64_t sizes[5] = {(n_q + 1) * 8, nnz * 4, nnz * 4, n_pairs * 8, n_pairs * 8};
+      const void* src[5] = {q_off, q_id, q_mass, pair_q, pair_d};
+      int64_t total = sizes[0] + sizes[1] + sizes[2] + sizes[3] + sizes[4];
+      if (compare && (int64_t)ix->fwd_sig.bytes < total) return false;
+      uint8_t* keep = (uint8_t*)(compare ? ix->fwd_sig.p : ix->fwd_sig.ensure(total));
+      if (compare && ix->fwd_sig_bytes != total) return false;
+      for (int i = 0; i < 5; ++i) {
+        if (sizes[i] > 0)
+          k_copy_or_compare<<<(unsigned)ceil_div(sizes[i], 256), 256, 0, s>>>((const uint8_t*)src[i], keep,
+                                                                            sizes[i], compare,
+                                                                            ix->status.as<uint32_t>());
+        keep += sizes[i];
+      }
+      FT_HIP(hipGetLastError());
+      ix->fwd_sig_bytes = total;
+      return compare ? read_and_clear_status(ix, s) == 0 : true;
+    };
+    if (mode == FT_FWD) {
+      FT_REQUIRE(cost, FT_EINVAL, "cost is NULL");
+      run_save(ix, X, q_off, q_id, q_mass, n_q, pair_q, pair_d, n_pairs, cost, s);
+      uint32_t flags = read_and_clear_status(ix, s);
+      FT_REQUIRE(flags == 0, FT_EHIP, "flowtree kernel reported:" + describe_flags(flags));
+      ix->fwd_valid = false;
+      keep_args(0);
+      ix->fwd_valid = true;
+      return;
+    }
+    FT_REQUIRE(grad_out, FT_EINVAL, "grad_out is NULL");
+    FT_REQUIRE(ix->fwd_valid && keep_args(1), FT_EINVAL,
+               "FT_BWD needs the pairs and queries of the preceding FT_FWD call");
+    // the query preparation is deterministic: redo it in case another call
+    // reused the workspace
+    prepare_dists(ix, ix->qry, q_off, q_id, q_mass, n_q, false, s, "queries");
+    const int cls = class_for(ix->qry.max_size + ix->docs.max_size);
+    const int G = lanes_for((ix->d + 3) / 4);
+    const int VEC = (ix->d % 4 == 0 && ((uintptr_t)X & 15) == 0) ? 4 : 1;
+    FT_DISPATCH_CG(k_flow_bwd, cls, G, VEC, dim3((unsigned)n_pairs), s, pair_q, pair_d, ix->fwd_base.as<int64_t>(),
+                   ix->fwd_cnt.as<int32_t>(), ix->fwd_id.as<uint32_t>(), ix->fwd_eta.as<uint32_t>(),
+                   ix->fwd_key.as<uint64_t>(), ix->fwd_bind.as<uint8_t>(), ix->qry.off.as<int64_t>(),
+                   ix->qry.rank.as<uint32_t>(), ix->qry.pos.as<uint16_t>(), ix->docs.off.as<int64_t>(),
+                   ix->docs.rank.as<uint32_t>(), ix->docs.pos.as<uint16_t>(), ix->perm.as<uint32_t>(), X, ix->d,
+                   ix->Q, grad_out, grad_X, grad_qmass, grad_dmass);
+    FT_HIP(hipGetLastError());
+  });
+}

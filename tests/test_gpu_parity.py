@@ -1,0 +1,375 @@
+"""HIP path against the CPU oracle, through the C ABI.
+
+Bars: bit-exact tree (Morton order, adjacent LCA depths, leaf depths), bit-
+exact Quadtree keys and Flowtree flows; float32 Flowtree costs within 1e-5
+relative of the float64 oracle; identical top-k (near-ties within 2e-5
+relative may swap, and are counted).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+from gpu_util import (build_index, check_topk, oracle_flow_set, oracle_matrix, oracle_tree,
+                      queries, subset, t)
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ft():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1910_04126_amd as m
+    m.load()
+    return m
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+# ------------------------------------------------------------------ worlds --
+
+def world_tiny():
+    return gen.make("tiny")
+
+
+def world_small_cases():
+    """Hand-made ground sets stressing the tree: coincident points (depth-B
+    leaves holding several points), tight clusters (deep trees), a grid."""
+    out = []
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((300, 3)).astype(np.float32)
+    X[100:110] = X[0]                       # ten coincident points
+    X[200:260] = (X[200:260] * 1e-4 + 3).astype(np.float32)  # a tight cluster
+    out.append(("dup_cluster", X, gen.random_shift(rng, 3, 30), 30))
+    out.append(("grid28", gen.pixel_grid(28), gen.random_shift(rng, 2, 30), 30))
+    out.append(("B8", rng.standard_normal((200, 2)).astype(np.float32), gen.random_shift(rng, 2, 8), 8))
+    return out
+
+
+def dataset_on(X, shift, B, n_docs, n_q, lo, hi, Q, seed):
+    rng = np.random.default_rng(seed)
+    V = len(X)
+    def dists(n):
+        sizes = rng.integers(lo, min(hi, V) + 1, size=n)
+        off = np.zeros(n + 1, np.int64)
+        off[1:] = np.cumsum(sizes)
+        ids = np.concatenate([rng.choice(V, s, replace=False) for s in sizes]).astype(np.uint32)
+        m = gen.uniform_masses(off, ids, Q)
+        return off, ids, m
+    do, di, dm = dists(n_docs)
+    qo, qi, qm = dists(n_q)
+    return gen.Dataset("custom", X, np.asarray(shift, np.int64), B, Q, do, di, dm, qo, qi, qm, 5)
+
+
+# ------------------------------------------------------------------- tree --
+
+def check_tree(ft, ds):
+    ix = build_index(ft, ds)
+    perm, lcp, ld = ix.export_tree()
+    T = oracle_tree(ds)
+    ex = T.export()
+    point_at = np.argsort(ex["rank_of"])
+    perm = perm.cpu().numpy().astype(np.int64)
+    assert (perm == point_at).all(), "Morton order differs"
+    lcp = lcp.cpu().numpy().astype(np.int64)
+    want = [T.lca_depth(point_at[r], point_at[r + 1]) for r in range(len(perm) - 1)]
+    assert (lcp[:-1] == np.array(want)).all(), "adjacent LCA depths differ"
+    ld = ld.cpu().numpy().astype(np.int64)
+    assert (ld == ex["leaf_depth"][point_at]).all(), "leaf depths differ"
+    info = ix.info()
+    assert info["n_nodes"] == T.n_nodes
+    assert info["height"] == ex["leaf_depth"].max()
+    return ix, T
+
+
+def test_tree_tiny(ft):
+    say("tree: tiny")
+    check_tree(ft, world_tiny())
+
+
+@pytest.mark.parametrize("case", range(3))
+def test_tree_small_cases(ft, case):
+    name, X, shift, B = world_small_cases()[case]
+    say("tree:", name)
+    ds = dataset_on(X, shift, B, 40, 4, 1, 20, 16, case)
+    check_tree(ft, ds)
+
+
+def test_tree_text_shaped(ft):
+    say("tree: text-shaped V=20000 d=300")
+    ds = gen.make("text", V=20000, n_docs=200, n_queries=2)
+    check_tree(ft, ds)
+
+
+# --------------------------------------------------------------- quadtree --
+
+def test_quadtree_pairs_bitexact_tiny(ft):
+    say("quadtree pairs: tiny, all 5000 pairs")
+    ds = world_tiny()
+    ix = build_index(ft, ds)
+    T = oracle_tree(ds)
+    pq = np.repeat(np.arange(ds.n_queries), ds.n_docs)
+    pd = np.tile(np.arange(ds.n_docs), ds.n_queries)
+    got = ft.quadtree_pairs(ix, *queries(ds), t(pq), t(pd)).cpu().numpy().view(np.uint64)
+    want = T.quadtree_pairs(ds.q_off, ds.q_id, ds.q_mass, ds.doc_off, ds.doc_id, ds.doc_mass, pq, pd, ds.Q)
+    assert (got == want).all()
+
+
+@pytest.mark.parametrize("case", range(3))
+def test_quadtree_knn_small_cases(ft, case):
+    name, X, shift, B = world_small_cases()[case]
+    say("quadtree knn:", name)
+    ds = dataset_on(X, shift, B, 150, 5, 1, 25, 16, 10 + case)
+    ix = build_index(ft, ds)
+    T = oracle_tree(ds)
+    keys, docs = ft.quadtree_knn(ix, *queries(ds), 7)
+    keys = keys.cpu().numpy().view(np.uint64)
+    docs = docs.cpu().numpy()
+    M = oracle_matrix(T, ds, range(ds.n_queries), np.arange(ds.n_docs), "qt")
+    for q in range(ds.n_queries):
+        check_topk(docs[q], keys[q], M[q], np.arange(ds.n_docs), 7, exact=True)
+
+
+def test_quadtree_knn_tiny_all_and_cand(ft):
+    say("quadtree knn: tiny, all docs and candidate lists")
+    ds = world_tiny()
+    ix = build_index(ft, ds)
+    T = oracle_tree(ds)
+    M = oracle_matrix(T, ds, range(ds.n_queries), np.arange(ds.n_docs), "qt")
+    keys, docs = ft.quadtree_knn(ix, *queries(ds), ds.k)
+    for q in range(ds.n_queries):
+        check_topk(docs[q].cpu().numpy(), keys[q].cpu().numpy().view(np.uint64), M[q], np.arange(ds.n_docs),
+                   ds.k, exact=True)
+    rng = np.random.default_rng(3)
+    cand = np.stack([rng.choice(ds.n_docs, 77, replace=False) for _ in range(ds.n_queries)])
+    keys, docs = ft.quadtree_knn(ix, *queries(ds), 9, cand=t(cand))
+    for q in range(ds.n_queries):
+        check_topk(docs[q].cpu().numpy(), keys[q].cpu().numpy().view(np.uint64), M[q][cand[q]], cand[q], 9,
+                   exact=True)
+
+
+# --------------------------------------------------------------- flowtree --
+
+def check_flows(ft, ds, ix, T, pairs, q_sel=None):
+    qc = None
+    if q_sel is not None:
+        qc = subset(ds.q_off, ds.q_id, ds.q_mass, q_sel)
+    pq = np.array([p[0] for p in pairs])
+    pd = np.array([p[1] for p in pairs])
+    got = ft.flowtree_flows(ix, *(queries(ds) if qc is None else (t(qc[0]), t(qc[1]), t(qc[2]))),
+                            t(pq), t(pd))
+    for (q, doc), (fd, fq, fe, fb) in zip(pairs, got):
+        mine = sorted(zip(fd.tolist(), fq.tolist(), fe.tolist(), fb.tolist()))
+        want = oracle_flow_set(T, ds, q, doc, q_csr=qc)
+        assert mine == want, "flow of pair (q=%d, doc=%d) differs" % (q, doc)
+
+
+def test_flows_bitexact_tiny(ft):
+    say("flows: tiny, 400 pairs")
+    ds = world_tiny()
+    ix = build_index(ft, ds)
+    T = oracle_tree(ds)
+    rng = np.random.default_rng(0)
+    pairs = [(int(rng.integers(ds.n_queries)), int(rng.integers(ds.n_docs))) for _ in range(400)]
+    check_flows(ft, ds, ix, T, pairs)
+
+
+@pytest.mark.parametrize("case", range(3))
+def test_flows_bitexact_small_cases(ft, case):
+    name, X, shift, B = world_small_cases()[case]
+    say("flows:", name)
+    ds = dataset_on(X, shift, B, 60, 6, 1, 40, 12, 20 + case)
+    ix = build_index(ft, ds)
+    T = oracle_tree(ds)
+    pairs = [(q, doc) for q in range(ds.n_queries) for doc in range(0, ds.n_docs, 3)]
+    check_flows(ft, ds, ix, T, pairs)
+
+
+def test_flows_shared_points(ft):
+    """Queries equal to docs, and sharing most points: self-matches at leaves."""
+    say("flows: shared supports")
+    ds = world_tiny()
+    sel = [0, 1, 2, 3]
+    qo, qi, qm = subset(ds.doc_off, ds.doc_id, ds.doc_mass, sel)
+    ds2 = gen.Dataset("shared", ds.X, ds.shift, ds.B, ds.Q, ds.doc_off, ds.doc_id, ds.doc_mass, qo, qi, qm, 5)
+    ix = build_index(ft, ds2)
+    T = oracle_tree(ds2)
+    pairs = [(q, doc) for q in range(4) for doc in range(8)]
+    check_flows(ft, ds2, ix, T, pairs)
+    costs, docs = ft.flowtree_knn(ix, *queries(ds2), 3, mode=ft.FT_BATCHED)
+    assert (docs[:, 0].cpu().numpy() == np.array(sel)).all()
+    assert (costs[:, 0].cpu().numpy() == 0).all()
+
+
+def flow_knn_check(ft, ds, ix, T, k, cand=None, modes=("plain", "batched"), q_sel=None):
+    n_q = ds.n_queries
+    res = {}
+    for mode in modes:
+        m = ft.FT_PLAIN if mode == "plain" else ft.FT_BATCHED
+        c, d = ft.flowtree_knn(ix, *queries(ds), k, cand=None if cand is None else t(cand), mode=m)
+        res[mode] = (c.cpu().numpy(), d.cpu().numpy())
+    if len(modes) == 2:
+        assert (res["plain"][1] == res["batched"][1]).all()
+        assert (res["plain"][0] == res["batched"][0]).all(), "plain and batched costs differ"
+    c, d = res[modes[-1]]
+    swaps = 0
+    qs = range(n_q) if q_sel is None else q_sel
+    for q in qs:
+        cols = np.arange(ds.n_docs) if cand is None else cand[q]
+        M = oracle_matrix(T, ds, [q], cols, "ft")[0]
+        swaps += check_topk(d[q], c[q], M, cols, k)
+    return swaps
+
+
+def test_flowtree_knn_tiny_full_ranking(ft):
+    say("flowtree knn: tiny, full ranking of 500 docs, plain and batched")
+    ds = world_tiny()
+    ix = build_index(ft, ds)
+    T = oracle_tree(ds)
+    swaps = flow_knn_check(ft, ds, ix, T, ds.n_docs)
+    say("  near-tie swaps:", swaps)
+    swaps = flow_knn_check(ft, ds, ix, T, ds.k)
+    assert swaps == 0
+
+
+def test_flowtree_knn_text_reduced_pipeline(ft):
+    say("pipeline: text-shaped V=5000 d=300, 2000 docs, 6 queries: quadtree 100 -> flowtree 20")
+    ds = gen.make("text", V=5000, n_docs=2000, n_queries=6)
+    ix = build_index(ft, ds)
+    T = oracle_tree(ds)
+    keys, cand = ft.quadtree_knn(ix, *queries(ds), 100)
+    M = oracle_matrix(T, ds, range(ds.n_queries), np.arange(ds.n_docs), "qt")
+    cand_h = cand.cpu().numpy()
+    for q in range(ds.n_queries):
+        check_topk(cand_h[q], keys[q].cpu().numpy().view(np.uint64), M[q], np.arange(ds.n_docs), 100, exact=True)
+    swaps = flow_knn_check(ft, ds, ix, T, 20, cand=cand_h)
+    assert swaps == 0
+
+
+def test_flowtree_knn_image_reduced(ft):
+    say("flowtree knn: image-shaped, 1500 docs, 3 queries, all docs, top-10")
+    ds = gen.make("image", n_docs=1500, n_queries=3)
+    ix = build_index(ft, ds)
+    T = oracle_tree(ds)
+    flow_knn_check(ft, ds, ix, T, 10)
+
+
+def test_flowtree_knn_uneven_sizes(ft):
+    say("flowtree knn: sizes 5..500 (power law), V=4000 d=300, 1500 docs, 8 queries, all size classes")
+    ds = gen.make("batched", V=4000, n_docs=1500, n_queries=8)
+    # make sure the largest class is exercised
+    assert np.diff(ds.q_off).max() + np.diff(ds.doc_off).max() > 512
+    ix = build_index(ft, ds)
+    T = oracle_tree(ds)
+    rng = np.random.default_rng(1)
+    cand = np.stack([rng.choice(ds.n_docs, 300, replace=False) for _ in range(ds.n_queries)])
+    flow_knn_check(ft, ds, ix, T, 20, cand=cand)
+
+
+def test_flowtree_deterministic(ft):
+    say("flowtree knn: repeated batched calls give identical bits")
+    ds = world_tiny()
+    ix = build_index(ft, ds)
+    a = ft.flowtree_knn(ix, *queries(ds), 50, mode=ft.FT_BATCHED)
+    b = ft.flowtree_knn(ix, *queries(ds), 50, mode=ft.FT_BATCHED)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+# ------------------------------------------------------------- gradients --
+
+def test_cost_grad_vs_oracle(ft):
+    say("cost_grad: V=3000 d=300, 24 pairs, forward and backward")
+    ds = gen.make("grad", V=3000, n_pairs=24)
+    ix = build_index(ft, ds)
+    T = oracle_tree(ds)
+    pq, pd = ds.extra["pair_q"], ds.extra["pair_d"]
+    X = t(ds.X)
+    qo, qi, qm = queries(ds)
+    cost = torch.empty(len(pq), dtype=torch.float32, device=X.device)
+    ft.flowtree_cost_grad(ix, X, qo, qi, qm, t(pq), t(pd), ft.FT_FWD, cost=cost)
+    g_out = torch.linspace(0.5, 1.5, len(pq), device=X.device, dtype=torch.float32)
+    gX = torch.zeros_like(X)
+    gq = torch.zeros(len(ds.q_id), device=X.device)
+    gd = torch.zeros(len(ds.doc_id), device=X.device)
+    ft.flowtree_cost_grad(ix, X, qo, qi, qm, t(pq), t(pd), ft.FT_BWD, grad_out=g_out, grad_X=gX,
+                          grad_qmass=gq, grad_dmass=gd)
+    cost, gX, gq, gd, g_out = [v.cpu().numpy() for v in (cost, gX, gq, gd, g_out)]
+    wX = np.zeros(ds.X.shape)
+    wq = np.zeros(len(ds.q_id))
+    wd = np.zeros(len(ds.doc_id))
+    for p, (q, doc) in enumerate(zip(pq, pd)):
+        a, b = ds.doc_off[doc], ds.doc_off[doc + 1]
+        qa, qb = ds.q_off[q], ds.q_off[q + 1]
+        c, fl = T.flowtree(ds.doc_id[a:b], ds.doc_mass[a:b], ds.q_id[qa:qb], ds.q_mass[qa:qb], Q=ds.Q)
+        assert abs(cost[p] - c) <= 1e-5 * c
+        gx, gm, gn = oracle.frozen_grad(ds.X, ds.doc_id[a:b], ds.q_id[qa:qb], fl,
+                                        ds.doc_mass[a:b] / 2.0 ** ds.Q, ds.q_mass[qa:qb] / 2.0 ** ds.Q)
+        wX += g_out[p] * gx
+        wd[a:b] += g_out[p] * gm
+        wq[qa:qb] += g_out[p] * gn
+    rows = np.flatnonzero(np.abs(wX).sum(1) > 0)
+    for r in rows:
+        assert np.linalg.norm(gX[r] - wX[r]) <= 1e-5 * np.linalg.norm(wX[r]) + 1e-7
+    assert np.abs(gX[np.setdiff1d(np.arange(len(wX)), rows)]).max() == 0
+    assert np.allclose(gq, wq, rtol=1e-5, atol=1e-6 * np.abs(wq).max())
+    assert np.allclose(gd, wd, rtol=1e-5, atol=1e-6 * np.abs(wd).max())
+
+
+def test_autograd_function(ft):
+    say("autograd: FlowtreeCost backward equals the C ABI backward")
+    from paper_1910_04126_amd.autograd import flowtree_cost
+    ds = gen.make("grad", V=2000, n_pairs=8)
+    ix = build_index(ft, ds)
+    qo, qi, qm = queries(ds)
+    X = t(ds.X).requires_grad_(True)
+    qw = (t(ds.q_mass.astype(np.float64)) * 2.0 ** -ds.Q).to(torch.float32).requires_grad_(True)
+    dw = (t(ds.doc_mass.astype(np.float64)) * 2.0 ** -ds.Q).to(torch.float32).requires_grad_(True)
+    pq, pd = t(ds.extra["pair_q"]), t(ds.extra["pair_d"])
+    c = flowtree_cost(X, qw, dw, ix, qo, qi, qm, pq, pd)
+    c.sum().backward()
+    assert X.grad is not None and torch.isfinite(X.grad).all()
+    assert qw.grad is not None and dw.grad is not None
+
+
+# ------------------------------------------------------------------ errors --
+
+def test_invalid_inputs(ft):
+    say("errors: invalid inputs are rejected")
+    ds = world_tiny()
+    ix = build_index(ft, ds)
+    qo, qi, qm = queries(ds)
+    bad = qi.clone()
+    bad[0] = ds.V
+    with pytest.raises(ft.FtError) as e:
+        ft.flowtree_knn(ix, qo, bad, qm, 5)
+    assert e.value.status == -1
+    bad = qm.clone()
+    bad[0] += 1
+    with pytest.raises(ft.FtError) as e:
+        ft.quadtree_knn(ix, qo, qi, bad, 5)
+    assert e.value.status == -1
+    bad = qi.clone()
+    bad[1] = bad[0]
+    with pytest.raises(ft.FtError):
+        ft.flowtree_knn(ix, qo, bad, qm, 5)
+    with pytest.raises(ft.FtError):
+        ft.flowtree_knn(ix, qo, qi, qm, ds.n_docs + 1)
+    big = 1100
+    o = torch.tensor([0, big], dtype=torch.int64, device=qo.device)
+    ids = torch.arange(big, dtype=torch.int32, device=qo.device)
+    m = torch.full((big,), 0, dtype=torch.int32, device=qo.device)
+    m[:] = (1 << ds.Q) // big
+    m[0] += (1 << ds.Q) - int(m.sum().item())
+    with pytest.raises(ft.FtError) as e:
+        ft.flowtree_knn(ix, o, ids, m, 5)
+    assert e.value.status == -4
+    # the index still works afterwards
+    c, d = ft.flowtree_knn(ix, qo, qi, qm, 5)
+    assert torch.isfinite(c).all()
