@@ -373,3 +373,77 @@ def test_invalid_inputs(ft):
     # the index still works afterwards
     c, d = ft.flowtree_knn(ix, qo, qi, qm, 5)
     assert torch.isfinite(c).all()
+
+
+# ------------------------------------------------------- long-row select --
+
+def test_long_rows_select(ft):
+    say("select: 6000 docs ranked in full (window select), quadtree and flowtree")
+    ds = gen.make("text", V=4000, d=64, n_docs=6000, n_queries=3)
+    ix = build_index(ft, ds)
+    T = oracle_tree(ds)
+    docs = np.arange(ds.n_docs)
+    keys, kd = ft.quadtree_knn(ix, *queries(ds), 300)
+    M = oracle_matrix(T, ds, range(3), docs, "qt")
+    for q in range(3):
+        check_topk(kd[q].cpu().numpy(), keys[q].cpu().numpy().view(np.uint64), M[q], docs, 300, exact=True)
+    c, d = ft.flowtree_knn(ix, *queries(ds), 50, mode=ft.FT_BATCHED)
+    F = oracle_matrix(T, ds, range(3), docs, "ft")
+    for q in range(3):
+        check_topk(d[q].cpu().numpy(), c[q].cpu().numpy(), F[q], docs, 50)
+
+
+@pytest.mark.parametrize("reps", [1500, 2040, 2600])
+def test_long_rows_tie_bucket_sizes(ft, reps):
+    """Tie buckets just below, at and above the LDS capacity of the window
+    select (2048 entries)."""
+    say("select: %d identical docs among %d" % (reps, reps + 4200))
+    base = gen.make("tiny", n_docs=4200, n_queries=2)
+    one = base.doc_id[base.doc_off[3]:base.doc_off[4]]
+    onem = base.doc_mass[base.doc_off[3]:base.doc_off[4]]
+    sizes = np.concatenate([np.diff(base.doc_off), np.full(reps, len(one))])
+    off = np.zeros(len(sizes) + 1, np.int64)
+    off[1:] = np.cumsum(sizes)
+    ids = np.concatenate([base.doc_id, np.tile(one, reps)])
+    m = np.concatenate([base.doc_mass, np.tile(onem, reps)])
+    ds = gen.Dataset("ties", base.X, base.shift, base.B, base.Q, off, ids, m, base.q_off, base.q_id, base.q_mass, 5)
+    ix = build_index(ft, ds)
+    T = oracle_tree(ds)
+    docs = np.arange(ds.n_docs)
+    M = oracle_matrix(T, ds, range(2), docs, "qt")
+    for q in range(2):
+        kth = np.sort(M[q])
+        # choose k so that the k-th key is the duplicated one when possible
+        dup_key = M[q][-1]
+        k = int(min(1024, max(1, (M[q] < dup_key).sum() + 1)))
+        keys, kd = ft.quadtree_knn(ix, *queries(ds), k)
+        check_topk(kd[q].cpu().numpy(), keys[q].cpu().numpy().view(np.uint64), M[q], docs, k, exact=True)
+
+
+def test_long_rows_many_ties(ft):
+    """Thousands of identical docs give thousands of equal keys at the k-th
+    position: the window select hands the row to the radix fallback, and
+    ties must still go to the lowest doc indices."""
+    say("select: 5000 docs, 4200 identical (fallback path)")
+    base = gen.make("tiny", n_docs=800, n_queries=2)
+    reps = 4200
+    one = base.doc_id[base.doc_off[0]:base.doc_off[1]]
+    onem = base.doc_mass[base.doc_off[0]:base.doc_off[1]]
+    sizes = np.concatenate([np.full(reps, len(one)), np.diff(base.doc_off)])
+    off = np.zeros(len(sizes) + 1, np.int64)
+    off[1:] = np.cumsum(sizes)
+    ids = np.concatenate([np.tile(one, reps), base.doc_id])
+    m = np.concatenate([np.tile(onem, reps), base.doc_mass])
+    ds = gen.Dataset("ties", base.X, base.shift, base.B, base.Q, off, ids, m, base.q_off, base.q_id, base.q_mass, 5)
+    ix = build_index(ft, ds)
+    T = oracle_tree(ds)
+    docs = np.arange(ds.n_docs)
+    M = oracle_matrix(T, ds, range(2), docs, "qt")
+    F = oracle_matrix(T, ds, range(2), docs, "ft")
+    for k in (1000, 1024):
+        keys, kd = ft.quadtree_knn(ix, *queries(ds), k)
+        for q in range(2):
+            check_topk(kd[q].cpu().numpy(), keys[q].cpu().numpy().view(np.uint64), M[q], docs, k, exact=True)
+    c, d = ft.flowtree_knn(ix, *queries(ds), 1000, mode=ft.FT_BATCHED)
+    for q in range(2):
+        check_topk(d[q].cpu().numpy(), c[q].cpu().numpy(), F[q], docs, 1000)
