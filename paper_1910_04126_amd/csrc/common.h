@@ -129,8 +129,10 @@ struct ft_index {
   ft::DevBuf anc;       // u32 [height * V] index of the depth-(k+1) node of each rank
   ft::DevBuf status;    // u32 [8] validation flags and counters
   ft::Dists docs;
-  ft::DevBuf doc_tiles;  // Quadtree doc tiles for ranking all docs
-  int64_t doc_tiles_small = 0, doc_tiles_large = 0;
+  ft::DevBuf doc_tiles;    // Quadtree doc tiles for ranking all docs
+  ft::DevBuf doc_tables;   // per-doc hash tables of the embeddings
+  ft::DevBuf doc_tb_off;   // int64 [n_docs + 1] bucket offsets of the tables
+  int64_t doc_tiles_small = 0;
   // per-call workspaces
   ft::Dists qry;
   ft::DevBuf ws_keys, ws_cost, ws_tiles, ws_lists, ws_counts, ws_misc, ws_sel;

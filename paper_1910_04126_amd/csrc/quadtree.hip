@@ -113,84 +113,145 @@ __global__ __launch_bounds__(QT_THREADS) void k_qt_tile(
 
 // ------------------------------------------------------- doc-tile kernel --
 //
-// Ranking all docs: a workgroup holds the hash tables of T consecutive docs
-// (packed key | mass << 32 slots) and streams queries, whose embeddings are
-// small enough to stay in cache.  In a wavefront, lane l works for doc
-// t = l % T on the query entries l / T, l / T + 64 / T, ...; the 64 / T lanes
-// of a doc are then summed by xor-shuffles.  Every lane does the same number
-// of lookups, whatever the sizes.
+// Ranking all docs.  Every doc owns a hash table of its embedding, built once
+// per index in HBM: nb = max(2, nnz) buckets of two (key, mass) slots (load
+// at most 1/2), bucket = high half of (key * golden) * nb, linear probing
+// with wrap-around.  A workgroup copies the tables of T consecutive docs into
+// LDS and streams the (cache-resident) query embeddings; lane l works for doc
+// l % T on the query entries l / T, l / T + 64 / T, ..., four lookups in
+// flight, and the 64 / T lanes of a doc are summed by xor-shuffles.  One
+// 16-byte LDS read answers a lookup unless the bucket is full without the
+// key.  A bucket's second slot is only used once its first is taken, so an
+// empty second slot ends a miss.
 
-constexpr uint64_t EMPTY_SLOT = 0x00000000FFFFFFFFull;
-constexpr int QT_STAGE = 256;  // query entries staged per wavefront at a time
+constexpr uint32_t NO_KEY = 0xFFFFFFFEu;  // padding entry: never a node key
+constexpr uint32_t HASH_MUL = 0x9E3779B1u;
+constexpr int QT_BUCKETS = 4096;           // LDS buckets per workgroup (64 KiB)
+constexpr int QT_TILE_THREADS = 512;
 
 struct DocTile {
   int64_t d0;     // first doc
-  int32_t T;      // docs (power of two, <= 64)
-  int32_t lgcap;  // log2 slots per doc
+  int32_t T;      // docs (power of two, <= 32)
+  int32_t pad;
 };
 
-__device__ __forceinline__ uint32_t probe(const uint64_t* __restrict__ tab, int lgcap, uint32_t key) {
-  const uint32_t mask = (1u << lgcap) - 1;
-  uint32_t h = slot_hash(key, lgcap);
-  while (true) {
-    const uint64_t v = tab[h];
-    const uint32_t k = (uint32_t)v;
-    if (k == key) return (uint32_t)(v >> 32);
-    if (k == EMPTY_KEY) return 0u;
-    h = (h + 1) & mask;
+// One wavefront per doc: insert its embedding into its table.
+__global__ __launch_bounds__(64) void k_build_doc_tables(const int64_t* __restrict__ d_eoff,
+                                                         const uint32_t* __restrict__ d_ekey,
+                                                         const uint32_t* __restrict__ d_emass,
+                                                         const int64_t* __restrict__ tb_off, int64_t n,
+                                                         uint4* __restrict__ tables) {
+  const int64_t d = blockIdx.x;
+  if (d >= n) return;
+  uint4* tb = tables + tb_off[d];
+  const uint32_t nb = (uint32_t)(tb_off[d + 1] - tb_off[d]);
+  for (uint32_t i = threadIdx.x; i < nb; i += 64) tb[i] = make_uint4(EMPTY_KEY, 0u, EMPTY_KEY, 0u);
+  __syncthreads();
+  for (int64_t e = d_eoff[d] + threadIdx.x; e < d_eoff[d + 1]; e += 64) {
+    const uint32_t key = d_ekey[e];
+    uint32_t h = __umulhi(key * HASH_MUL, nb);
+    while (true) {
+      uint32_t* w = reinterpret_cast<uint32_t*>(&tb[h]);
+      if (atomicCAS(&w[0], EMPTY_KEY, key) == EMPTY_KEY) {
+        w[1] = d_emass[e];
+        break;
+      }
+      if (atomicCAS(&w[2], EMPTY_KEY, key) == EMPTY_KEY) {
+        w[3] = d_emass[e];
+        break;
+      }
+      h = h + 1 == nb ? 0 : h + 1;
+    }
   }
 }
 
-template <int SLOTS>
-__global__ __launch_bounds__(QT_THREADS) void k_qt_doctile(
-    const DocTile* __restrict__ tiles, const int64_t* __restrict__ d_eoff, const uint32_t* __restrict__ d_ekey,
-    const uint32_t* __restrict__ d_emass, const uint64_t* __restrict__ d_S, const int64_t* __restrict__ q_eoff,
-    const uint32_t* __restrict__ q_ekey, const uint32_t* __restrict__ q_emass, const uint64_t* __restrict__ q_S,
-    int64_t q_begin, int64_t q_end, int64_t q_per_block, int64_t n_docs, int B, uint64_t* __restrict__ keys) {
-  __shared__ uint64_t tab[SLOTS];
-  __shared__ uint64_t stage[QT_THREADS / 64][QT_STAGE];
+// Query entries with their hash product and weight shift precomputed.
+__global__ void k_stage_query_entries(const uint32_t* __restrict__ ekey, const uint32_t* __restrict__ emass,
+                                      int64_t nnz, int B, uint4* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nnz) return;
+  const uint32_t key = ekey[e];
+  out[e] = make_uint4(key, emass[e], key * HASH_MUL, (uint32_t)(B - (int)(key >> KEY_DEPTH_SHIFT)));
+}
+
+__global__ __launch_bounds__(QT_TILE_THREADS) void k_qt_doctile(
+    const DocTile* __restrict__ tiles, const uint4* __restrict__ tables, const int64_t* __restrict__ tb_off,
+    const uint64_t* __restrict__ d_S, const int64_t* __restrict__ q_eoff, const uint4* __restrict__ q_ent,
+    const uint64_t* __restrict__ q_S, int64_t q_begin, int64_t q_end, int64_t q_per_block, int64_t n_docs,
+    uint64_t* __restrict__ keys) {
+  __shared__ uint4 tab[QT_BUCKETS];
   const DocTile tile = tiles[blockIdx.x];
-  const int cap = 1 << tile.lgcap;
-  for (int i = threadIdx.x; i < tile.T * cap; i += blockDim.x) tab[i] = EMPTY_SLOT;
-  __syncthreads();
-  for (int t = 0; t < tile.T; ++t) {
-    const int64_t doc = tile.d0 + t;
-    uint64_t* base = tab + t * cap;
-    for (int64_t e = d_eoff[doc] + threadIdx.x; e < d_eoff[doc + 1]; e += blockDim.x) {
-      const uint32_t key = d_ekey[e];
-      const uint64_t v = ((uint64_t)d_emass[e] << 32) | key;
-      uint32_t h = slot_hash(key, tile.lgcap);
-      while (atomicCAS((unsigned long long*)&base[h], EMPTY_SLOT, v) != EMPTY_SLOT) h = (h + 1) & (cap - 1);
-    }
-  }
+  const int64_t base = tb_off[tile.d0];
+  const int nbt = (int)(tb_off[tile.d0 + tile.T] - base);
+  for (int i = threadIdx.x; i < nbt; i += blockDim.x) tab[i] = tables[base + i];
   __syncthreads();
   const int lane = lane_id(), w = threadIdx.x >> 6;
+  constexpr int NW = QT_TILE_THREADS / 64;
   const int T = tile.T, J = 64 / T;
   const int t = lane & (T - 1), j0 = lane / T;
-  const uint64_t* mytab = tab + t * cap;
   const int64_t doc = tile.d0 + t;
+  const uint4* tb = tab + (tb_off[doc] - base);
+  const uint32_t nb = (uint32_t)(tb_off[doc + 1] - tb_off[doc]);
   const uint64_t Sd = d_S[doc];
-  uint64_t* st = stage[w];
   const int64_t qa = q_begin + (int64_t)blockIdx.y * q_per_block;
   const int64_t qb = min(q_end, qa + q_per_block);
-  for (int64_t q = qa + w; q < qb; q += QT_THREADS / 64) {
+  constexpr int U = 4;  // lookups in flight per lane
+  for (int64_t q = qa + w; q < qb; q += NW) {
     const int64_t e0 = q_eoff[q];
     const int ne = (int)(q_eoff[q + 1] - e0);
+    const uint4* qe = q_ent + e0;
     uint64_t acc = 0;
-    for (int c0 = 0; c0 < ne; c0 += QT_STAGE) {
-      const int cn = min(QT_STAGE, ne - c0);
-      __builtin_amdgcn_wave_barrier();
-      for (int i = lane; i < cn; i += 64) st[i] = ((uint64_t)q_emass[e0 + c0 + i] << 32) | q_ekey[e0 + c0 + i];
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      for (int i = j0; i < cn; i += J) {
-        const uint64_t ent = st[i];
-        const uint32_t key = (uint32_t)ent;
-        const uint32_t b = probe(mytab, tile.lgcap, key);
-        const uint32_t a = (uint32_t)(ent >> 32);
-        acc += (uint64_t)(a < b ? a : b) << (B - (int)(key >> KEY_DEPTH_SHIFT));
+    for (int i0 = j0; i0 < ne; i0 += U * J) {
+      uint4 en[U];
+      uint4 v[U];
+      uint32_t bk[U];
+      // the entry array is padded, so these loads never leave it; entries past
+      // the query's end are turned into padding keys
+#pragma unroll
+      for (int u = 0; u < U; ++u) en[u] = qe[i0 + u * J];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        en[u].x = i0 + u * J < ne ? en[u].x : NO_KEY;
+        bk[u] = __umulhi(en[u].z, nb);
       }
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = tb[bk[u]];
+      uint32_t m[U];
+      uint32_t pend = 0;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t key = en[u].x;
+        const bool hx = v[u].x == key, hz = v[u].z == key;
+        m[u] = hx ? v[u].y : (hz ? v[u].w : 0u);
+        const bool more = !hx & !hz & (v[u].z != EMPTY_KEY) & (key != NO_KEY);
+        pend |= (uint32_t)more << u;
+      }
+      // a full bucket without the key: continue in the next buckets
+      while (pend) {
+        const int u = __builtin_ctz(pend);
+        const uint32_t key = en[0].x * (u == 0) + en[1].x * (u == 1) + en[2].x * (u == 2) + en[3].x * (u == 3);
+        uint32_t b = bk[0] * (u == 0) + bk[1] * (u == 1) + bk[2] * (u == 2) + bk[3] * (u == 3);
+        uint32_t got = 0;
+        while (true) {
+          b = b + 1 == nb ? 0 : b + 1;
+          const uint4 x = tb[b];
+          if (x.x == key) {
+            got = x.y;
+            break;
+          }
+          if (x.z == key) {
+            got = x.w;
+            break;
+          }
+          if (x.z == EMPTY_KEY) break;
+        }
+#pragma unroll
+        for (int uu = 0; uu < U; ++uu)
+          if (uu == u) m[uu] = got;
+        pend &= pend - 1;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) acc += (uint64_t)(en[u].y < m[u] ? en[u].y : m[u]) << en[u].w;
     }
     for (int o = T; o < 64; o <<= 1) acc += __shfl_xor(acc, o, 64);
     if (j0 == 0) keys[(q - q_begin) * n_docs + doc] = q_S[q] + Sd - 2 * acc;
@@ -243,49 +304,39 @@ void check_indices(ft_index* ix, const int64_t* v, int64_t n, int64_t bound, hip
 
 constexpr int SLOTS_SMALL = 4096, SLOTS_LARGE = 8192;
 
-// Doc tiles for ranking all docs, planned once per index: consecutive docs
-// share a tile while T * cap fits SLOTS_SMALL (docs needing more go alone
-// into SLOTS_LARGE tiles).  Returns the number of small tiles; large ones
-// follow in the same array.
-static void plan_doc_tiles(ft_index* ix, hipStream_t s) {
-  if (ix->doc_tiles_small + ix->doc_tiles_large > 0) return;
+// Doc tables and tiles for ranking all docs, made once per index: table
+// sizes from the embedding sizes, tables built on the device, tiles of up to
+// 32 consecutive docs whose tables fit QT_BUCKETS.
+static void prepare_doc_tables(ft_index* ix, hipStream_t s) {
+  if (ix->doc_tiles_small > 0) return;
   const int64_t n = ix->docs.n;
-  std::vector<int64_t> eoff(n + 1);
+  std::vector<int64_t> eoff(n + 1), tb(n + 1);
   FT_HIP(hipMemcpyAsync(eoff.data(), ix->docs.ecnt.p, (n + 1) * 8, hipMemcpyDeviceToHost, s));
   FT_HIP(hipStreamSynchronize(s));
-  auto need_lg = [&](int64_t d) {
-    int64_t ne = eoff[d + 1] - eoff[d];
-    int l = 1;
-    while ((1ll << l) < 2 * ne) ++l;
-    return l;
-  };
-  std::vector<DocTile> small, large;
+  tb[0] = 0;
+  for (int64_t d = 0; d < n; ++d) {
+    const int64_t nb = std::max<int64_t>(2, eoff[d + 1] - eoff[d]);
+    FT_REQUIRE(nb <= QT_BUCKETS, FT_ERANGE, "a dataset distribution touches more than 4096 tree cells");
+    tb[d + 1] = tb[d] + nb;
+  }
+  std::vector<DocTile> tiles;
   int64_t d = 0;
   while (d < n) {
-    int lg = need_lg(d);
-    if ((1ll << lg) > SLOTS_SMALL) {
-      FT_REQUIRE((1ll << lg) <= SLOTS_LARGE, FT_ERANGE, "a dataset distribution touches more than 4096 tree cells");
-      large.push_back(DocTile{d, 1, lg});
-      ++d;
-      continue;
-    }
     int T = 1;
-    while (T * 2 <= 64 && d + 2 * T <= n) {
-      int lg2 = lg;
-      for (int64_t x = d + T; x < d + 2 * T; ++x) lg2 = std::max(lg2, need_lg(x));
-      if (((int64_t)(2 * T) << lg2) > SLOTS_SMALL) break;
-      T *= 2;
-      lg = lg2;
-    }
-    small.push_back(DocTile{d, T, lg});
+    while (T * 2 <= 32 && d + 2 * T <= n && tb[d + 2 * T] - tb[d] <= QT_BUCKETS) T *= 2;
+    tiles.push_back(DocTile{d, T, 0});
     d += T;
   }
-  ix->doc_tiles_small = (int64_t)small.size();
-  ix->doc_tiles_large = (int64_t)large.size();
-  small.insert(small.end(), large.begin(), large.end());
-  DocTile* dt = (DocTile*)ix->doc_tiles.ensure(small.size() * sizeof(DocTile));
-  FT_HIP(hipMemcpyAsync(dt, small.data(), small.size() * sizeof(DocTile), hipMemcpyHostToDevice, s));
+  int64_t* dtb = (int64_t*)ix->doc_tb_off.ensure((n + 1) * 8);
+  FT_HIP(hipMemcpyAsync(dtb, tb.data(), (n + 1) * 8, hipMemcpyHostToDevice, s));
+  uint4* tables = (uint4*)ix->doc_tables.ensure(tb[n] * sizeof(uint4));
+  k_build_doc_tables<<<(unsigned)n, 64, 0, s>>>(ix->docs.ecnt.as<int64_t>(), ix->docs.ekey.as<uint32_t>(),
+                                                ix->docs.emass.as<uint32_t>(), dtb, n, tables);
+  FT_HIP(hipGetLastError());
+  DocTile* dt = (DocTile*)ix->doc_tiles.ensure(tiles.size() * sizeof(DocTile));
+  FT_HIP(hipMemcpyAsync(dt, tiles.data(), tiles.size() * sizeof(DocTile), hipMemcpyHostToDevice, s));
   FT_HIP(hipStreamSynchronize(s));
+  ix->doc_tiles_small = (int64_t)tiles.size();
 }
 
 }  // namespace ft
@@ -314,25 +365,27 @@ extern "C" ft_status ft_quadtree_knn(ft_index* ix, const int64_t* q_off, const u
     // query chunks bound the key buffer to about 4 GiB
     const int64_t rows_per_chunk = std::max<int64_t>(1, std::min<int64_t>(n_q, (int64_t(1) << 29) / n_cols));
     uint64_t* keys = (uint64_t*)ix->ws_keys.ensure(rows_per_chunk * n_cols * 8);
-    if (!cand) plan_doc_tiles(ix, s);
+    uint4* q_ent = nullptr;
+    if (!cand) {
+      prepare_doc_tables(ix, s);
+      // padded by the furthest a lookup group can reach past a query's end
+      q_ent = (uint4*)ix->ws_misc.ensure((ix->qry.emb_nnz + 4 * 64) * sizeof(uint4));
+      FT_HIP(hipMemsetAsync(q_ent + ix->qry.emb_nnz, 0, 4 * 64 * sizeof(uint4), s));
+      if (ix->qry.emb_nnz > 0)
+        k_stage_query_entries<<<(unsigned)ceil_div(ix->qry.emb_nnz, 256), 256, 0, s>>>(
+            ix->qry.ekey.as<uint32_t>(), ix->qry.emass.as<uint32_t>(), ix->qry.emb_nnz, ix->B, q_ent);
+      FT_HIP(hipGetLastError());
+    }
     for (int64_t r0 = 0; r0 < n_q; r0 += rows_per_chunk) {
       const int64_t r1 = std::min(n_q, r0 + rows_per_chunk);
       if (!cand) {
-        // all docs: doc tiles in LDS, queries streamed
-        const int64_t qpb = 128;
-        const DocTile* dt = ix->doc_tiles.as<DocTile>();
+        // all docs: doc tables in LDS, queries streamed
+        const int64_t qpb = 256;
         const unsigned gy = (unsigned)ceil_div(r1 - r0, qpb);
-        if (ix->doc_tiles_small)
-          k_qt_doctile<SLOTS_SMALL><<<dim3((unsigned)ix->doc_tiles_small, gy), QT_THREADS, 0, s>>>(
-              dt, ix->docs.ecnt.as<int64_t>(), ix->docs.ekey.as<uint32_t>(), ix->docs.emass.as<uint32_t>(),
-              ix->docs.S.as<uint64_t>(), ix->qry.ecnt.as<int64_t>(), ix->qry.ekey.as<uint32_t>(),
-              ix->qry.emass.as<uint32_t>(), ix->qry.S.as<uint64_t>(), r0, r1, qpb, n_cols, ix->B, keys);
-        if (ix->doc_tiles_large)
-          k_qt_doctile<SLOTS_LARGE><<<dim3((unsigned)ix->doc_tiles_large, gy), QT_THREADS, 0, s>>>(
-              dt + ix->doc_tiles_small, ix->docs.ecnt.as<int64_t>(), ix->docs.ekey.as<uint32_t>(),
-              ix->docs.emass.as<uint32_t>(), ix->docs.S.as<uint64_t>(), ix->qry.ecnt.as<int64_t>(),
-              ix->qry.ekey.as<uint32_t>(), ix->qry.emass.as<uint32_t>(), ix->qry.S.as<uint64_t>(), r0, r1, qpb,
-              n_cols, ix->B, keys);
+        k_qt_doctile<<<dim3((unsigned)ix->doc_tiles_small, gy), QT_TILE_THREADS, 0, s>>>(
+            ix->doc_tiles.as<DocTile>(), ix->doc_tables.as<uint4>(), ix->doc_tb_off.as<int64_t>(),
+            ix->docs.S.as<uint64_t>(), ix->qry.ecnt.as<int64_t>(), q_ent, ix->qry.S.as<uint64_t>(), r0, r1, qpb,
+            n_cols, keys);
         FT_HIP(hipGetLastError());
       } else {
         // candidate lists: one query per workgroup, its table in LDS
