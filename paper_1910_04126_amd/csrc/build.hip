@@ -428,7 +428,10 @@ __global__ __launch_bounds__(64) void k_prep_sort(
 }
 
 // One wavefront per distribution: write the l1-embedding entries (node key,
-// node mass) and the weighted total S = sum 2^(B-depth) * mass.
+// node mass) depth by depth (all depth-1 cells first), and the weighted total
+// S = sum 2^(B-depth) * mass.  Item t opens the cells of depths
+// (lcp(t-1, t), leaf depth of t]; a cell's mass runs over the following items
+// while their adjacent LCA depth stays >= its depth.
 __global__ __launch_bounds__(64) void k_emb_fill(
     const int64_t* __restrict__ off, const uint32_t* __restrict__ rank, const uint32_t* __restrict__ mass,
     const uint8_t* __restrict__ lcp, int64_t n, const int64_t* __restrict__ eoff,
@@ -441,26 +444,32 @@ __global__ __launch_bounds__(64) void k_emb_fill(
   const int s = (int)(off[j + 1] - a);
   const int C = (s + 63) / 64;
   const int t0 = min(s, lane * C), t1 = min(s, t0 + C);
-  int64_t mine = 0;
-  for (int t = t0; t < t1; ++t) {
-    int prev = t > 0 ? lcp[a + t - 1] : 0;
-    int ld = leafd[rank[a + t]];
-    mine += ld > prev ? ld - prev : 0;
-  }
-  int64_t base = wave_incl_sum(mine) - mine + eoff[j];
+  int maxd = 0;
+  for (int t = t0; t < t1; ++t) maxd = max(maxd, (int)leafd[rank[a + t]]);
+  maxd = wave_max(maxd);
+  int64_t base = eoff[j];
   uint64_t Ssum = 0;
-  for (int t = t0; t < t1; ++t) {
-    uint32_t r = rank[a + t];
-    int prev = t > 0 ? lcp[a + t - 1] : 0;
-    int ld = leafd[r];
-    for (int k = prev + 1; k <= ld; ++k) {
-      uint64_t m = mass[a + t];
-      for (int u = t; u + 1 < s && lcp[a + u] >= k; ++u) m += mass[a + u + 1];
-      ekey[base] = ((uint32_t)k << KEY_DEPTH_SHIFT) | anc[(int64_t)(k - 1) * V + r];
-      emass[base] = (uint32_t)m;
-      Ssum += m << (B - k);
-      ++base;
+  for (int k = 1; k <= maxd; ++k) {
+    int mine = 0;
+    for (int t = t0; t < t1; ++t) {
+      const int prev = t > 0 ? lcp[a + t - 1] : 0;
+      mine += (prev < k && k <= (int)leafd[rank[a + t]]) ? 1 : 0;
     }
+    const int incl = wave_incl_sum(mine);
+    int64_t pos = base + incl - mine;
+    for (int t = t0; t < t1; ++t) {
+      const uint32_t r = rank[a + t];
+      const int prev = t > 0 ? lcp[a + t - 1] : 0;
+      if (prev < k && k <= (int)leafd[r]) {
+        uint64_t m = mass[a + t];
+        for (int u = t; u + 1 < s && lcp[a + u] >= k; ++u) m += mass[a + u + 1];
+        ekey[pos] = ((uint32_t)k << KEY_DEPTH_SHIFT) | anc[(int64_t)(k - 1) * V + r];
+        emass[pos] = (uint32_t)m;
+        Ssum += m << (B - k);
+        ++pos;
+      }
+    }
+    base += __shfl(incl, 63, 64);
   }
   Ssum = wave_sum(Ssum);
   if (lane == 0) S[j] = Ssum;
@@ -526,7 +535,7 @@ extern "C" const char* ft_last_error(void) { return ft::g_last_error.c_str(); }
 extern "C" void ft_free(ft_index* ix) {
   if (!ix) return;
   ix->graphs.reset();
-  for (DevBuf* b : {&ix->doc_tiles, &ix->doc_tables, &ix->doc_tb_off, &ix->Xm, &ix->perm, &ix->inv, &ix->st, &ix->leafd, &ix->anc, &ix->status, &ix->ws_keys,
+  for (DevBuf* b : {&ix->post, &ix->post_dir, &ix->post_cbase, &ix->Xm, &ix->perm, &ix->inv, &ix->st, &ix->leafd, &ix->anc, &ix->status, &ix->ws_keys,
                     &ix->ws_cost, &ix->ws_tiles, &ix->ws_lists, &ix->ws_counts, &ix->ws_misc, &ix->ws_sel,
                     &ix->fwd_id, &ix->fwd_eta, &ix->fwd_key, &ix->fwd_bind, &ix->fwd_cnt, &ix->fwd_base, &ix->fwd_sig})
     b->release();
@@ -661,6 +670,7 @@ extern "C" ft_status ft_build_tree(const float* X, int64_t V, int32_t d, const i
       FT_HIP(hipFree(stmp));
       ix->n_nodes = 1;
       for (int k = 1; k <= ix->height; ++k) ix->n_nodes += counts[k];
+      ix->depth_nodes = counts;
 
       // Morton-ordered, padded coordinates and the inverse permutation
       float* Xm = (float*)ix->Xm.ensure(V * ix->dp * sizeof(float));

@@ -129,10 +129,12 @@ struct ft_index {
   ft::DevBuf anc;       // u32 [height * V] index of the depth-(k+1) node of each rank
   ft::DevBuf status;    // u32 [8] validation flags and counters
   ft::Dists docs;
-  ft::DevBuf doc_tiles;    // Quadtree doc tiles for ranking all docs
-  ft::DevBuf doc_tables;   // per-doc hash tables of the embeddings
-  ft::DevBuf doc_tb_off;   // int64 [n_docs + 1] bucket offsets of the tables
-  int64_t doc_tiles_small = 0;
+  std::vector<int64_t> depth_nodes;  // [height + 1] nodes at each depth
+  // inverted doc lists for ranking all docs (built on first use)
+  ft::DevBuf post;         // uint2 [docs.emb_nnz] (doc within slice, cell mass), by slice, then cell
+  ft::DevBuf post_dir;     // u32 [post_nsl * post_cells] end offset of each cell's list in its slice
+  ft::DevBuf post_cbase;   // u32 [32] first cell number of each depth
+  int64_t post_slice = 0, post_cells = 0, post_nsl = 0;
   // per-call workspaces
   ft::Dists qry;
   ft::DevBuf ws_keys, ws_cost, ws_tiles, ws_lists, ws_counts, ws_misc, ws_sel;

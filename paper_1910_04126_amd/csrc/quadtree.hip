@@ -3,10 +3,10 @@
 // With each distribution stored as its l1 embedding (one entry per cell it
 // touches: node key, cell mass) and S = sum side * mass, the estimate is
 //     U = S_q + S_d - 2 * sum_{v in q and d} side(v) * min(m_q(v), m_d(v)),
-// so a pair costs one LDS hash lookup per entry of one side, accumulated as an
-// exact u64 key.  Ranking all docs holds doc tables in LDS and streams the
-// (cache-resident) queries; candidate lists hold one query table per
-// workgroup and stream its candidates.
+// accumulated as an exact u64 key.  Ranking all docs walks inverted doc lists
+// of the query's cells, so a pair costs only its shared cells; candidate
+// lists hold one query hash table per workgroup and stream the candidates'
+// entries through it.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -111,151 +111,174 @@ __global__ __launch_bounds__(QT_THREADS) void k_qt_tile(
   }
 }
 
-// ------------------------------------------------------- doc-tile kernel --
+// ------------------------------------------------- posting-list kernels --
 //
-// Ranking all docs.  Every doc owns a hash table of its embedding, built once
-// per index in HBM: nb = max(2, nnz) buckets of two (key, mass) slots (load
-// at most 1/2), bucket = high half of (key * golden) * nb, linear probing
-// with wrap-around.  A workgroup copies the tables of T consecutive docs into
-// LDS and streams the (cache-resident) query embeddings; lane l works for doc
-// l % T on the query entries l / T, l / T + 64 / T, ..., four lookups in
-// flight, and the 64 / T lanes of a doc are summed by xor-shuffles.  One
-// 16-byte LDS read answers a lookup unless the bucket is full without the
-// key.  A bucket's second slot is only used once its first is taken, so an
-// empty second slot ends a miss.
+// Ranking all docs.  A pair only gains from the cells it shares, and a
+// (query, doc) pair of word-embedding-shaped data shares about a tenth of the
+// query's cells, so the docs are stored inverted: cut into slices of S
+// consecutive docs, and inside a slice, for every tree cell, the list of
+// (doc within the slice, cell mass) of the docs that touch it.  Cells are
+// numbered densely (all depth-1 nodes, then depth 2, ...), so a slice's list
+// directory is a plain array of end offsets indexed by cell number.
+//
+// A workgroup takes one (query, slice): it looks up the query's cells in the
+// slice directory, cuts the non-empty lists into pieces of QP_PIECE entries,
+// and its wavefronts add 2^(B - depth) * min(query mass, doc mass) into one
+// u64 LDS counter per doc; the keys S_q + S_d - 2 * counter follow.
 
-constexpr uint32_t NO_KEY = 0xFFFFFFFEu;  // padding entry: never a node key
-constexpr uint32_t HASH_MUL = 0x9E3779B1u;
-constexpr int QT_BUCKETS = 4096;           // LDS buckets per workgroup (64 KiB)
-constexpr int QT_TILE_THREADS = 512;
+constexpr int QP_THREADS = 512;
+constexpr int QP_WAVES = QP_THREADS / 64;
+constexpr int QP_SLICE_MAX = 4096;  // docs per slice (u64 LDS counters)
+constexpr int QP_PIECE = 256;       // list entries per wavefront task
 
-struct DocTile {
-  int64_t d0;     // first doc
-  int32_t T;      // docs (power of two, <= 32)
-  int32_t pad;
-};
+// Slice size for n docs: at least 8 slices when the docs allow, at most
+// QP_SLICE_MAX docs each.
+inline int64_t post_slice_size(int64_t n) {
+  int64_t S = 64;
+  while (S * 2 <= QP_SLICE_MAX && S * 2 * 8 <= n) S *= 2;
+  return S;
+}
 
-// One wavefront per doc: insert its embedding into its table.
-__global__ __launch_bounds__(64) void k_build_doc_tables(const int64_t* __restrict__ d_eoff,
-                                                         const uint32_t* __restrict__ d_ekey,
-                                                         const uint32_t* __restrict__ d_emass,
-                                                         const int64_t* __restrict__ tb_off, int64_t n,
-                                                         uint4* __restrict__ tables) {
-  const int64_t d = blockIdx.x;
-  if (d >= n) return;
-  uint4* tb = tables + tb_off[d];
-  const uint32_t nb = (uint32_t)(tb_off[d + 1] - tb_off[d]);
-  for (uint32_t i = threadIdx.x; i < nb; i += 64) tb[i] = make_uint4(EMPTY_KEY, 0u, EMPTY_KEY, 0u);
-  __syncthreads();
-  for (int64_t e = d_eoff[d] + threadIdx.x; e < d_eoff[d + 1]; e += 64) {
-    const uint32_t key = d_ekey[e];
-    uint32_t h = __umulhi(key * HASH_MUL, nb);
-    while (true) {
-      uint32_t* w = reinterpret_cast<uint32_t*>(&tb[h]);
-      if (atomicCAS(&w[0], EMPTY_KEY, key) == EMPTY_KEY) {
-        w[1] = d_emass[e];
-        break;
-      }
-      if (atomicCAS(&w[2], EMPTY_KEY, key) == EMPTY_KEY) {
-        w[3] = d_emass[e];
-        break;
-      }
-      h = h + 1 == nb ? 0 : h + 1;
-    }
+__device__ __forceinline__ uint32_t cell_number(const uint32_t* __restrict__ cbase, uint32_t key) {
+  return cbase[key >> KEY_DEPTH_SHIFT] + (key & KEY_INDEX_MASK);
+}
+
+// Wavefront per doc: count the doc's cells into its slice's directory.
+__global__ __launch_bounds__(64) void k_post_count(const int64_t* __restrict__ eoff, const uint32_t* __restrict__ ekey,
+                                                   int64_t n_docs, int64_t S, int64_t n_cells,
+                                                   const uint32_t* __restrict__ cbase, uint32_t* __restrict__ dir) {
+  for (int64_t d = blockIdx.x; d < n_docs; d += gridDim.x) {
+    uint32_t* D = dir + (d / S) * n_cells;
+    for (int64_t e = eoff[d] + lane_id(); e < eoff[d + 1]; e += 64) atomicAdd(&D[cell_number(cbase, ekey[e])], 1u);
   }
 }
 
-// Query entries with their hash product and weight shift precomputed.
-__global__ void k_stage_query_entries(const uint32_t* __restrict__ ekey, const uint32_t* __restrict__ emass,
-                                      int64_t nnz, int B, uint4* __restrict__ out) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nnz) return;
-  const uint32_t key = ekey[e];
-  out[e] = make_uint4(key, emass[e], key * HASH_MUL, (uint32_t)(B - (int)(key >> KEY_DEPTH_SHIFT)));
-}
-
-__global__ __launch_bounds__(QT_TILE_THREADS) void k_qt_doctile(
-    const DocTile* __restrict__ tiles, const uint4* __restrict__ tables, const int64_t* __restrict__ tb_off,
-    const uint64_t* __restrict__ d_S, const int64_t* __restrict__ q_eoff, const uint4* __restrict__ q_ent,
-    const uint64_t* __restrict__ q_S, int64_t q_begin, int64_t q_end, int64_t q_per_block, int64_t n_docs,
-    uint64_t* __restrict__ keys) {
-  __shared__ uint4 tab[QT_BUCKETS];
-  const DocTile tile = tiles[blockIdx.x];
-  const int64_t base = tb_off[tile.d0];
-  const int nbt = (int)(tb_off[tile.d0 + tile.T] - base);
-  for (int i = threadIdx.x; i < nbt; i += blockDim.x) tab[i] = tables[base + i];
-  __syncthreads();
+// Workgroup per slice: exclusive scan of its directory counts, in place.
+__global__ __launch_bounds__(1024) void k_post_scan(uint32_t* __restrict__ dir, int64_t n_cells) {
+  __shared__ uint32_t wsum[16];
+  __shared__ uint32_t carry;
+  uint32_t* D = dir + (int64_t)blockIdx.x * n_cells;
   const int lane = lane_id(), w = threadIdx.x >> 6;
-  constexpr int NW = QT_TILE_THREADS / 64;
-  const int T = tile.T, J = 64 / T;
-  const int t = lane & (T - 1), j0 = lane / T;
-  const int64_t doc = tile.d0 + t;
-  const uint4* tb = tab + (tb_off[doc] - base);
-  const uint32_t nb = (uint32_t)(tb_off[doc + 1] - tb_off[doc]);
-  const uint64_t Sd = d_S[doc];
-  const int64_t qa = q_begin + (int64_t)blockIdx.y * q_per_block;
-  const int64_t qb = min(q_end, qa + q_per_block);
-  constexpr int U = 4;  // lookups in flight per lane
-  for (int64_t q = qa + w; q < qb; q += NW) {
-    const int64_t e0 = q_eoff[q];
-    const int ne = (int)(q_eoff[q + 1] - e0);
-    const uint4* qe = q_ent + e0;
-    uint64_t acc = 0;
-    for (int i0 = j0; i0 < ne; i0 += U * J) {
-      uint4 en[U];
-      uint4 v[U];
-      uint32_t bk[U];
-      // the entry array is padded, so these loads never leave it; entries past
-      // the query's end are turned into padding keys
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int64_t c0 = 0; c0 < n_cells; c0 += 4 * 1024) {
+    uint32_t v[4], t = 0;
 #pragma unroll
-      for (int u = 0; u < U; ++u) en[u] = qe[i0 + u * J];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        en[u].x = i0 + u * J < ne ? en[u].x : NO_KEY;
-        bk[u] = __umulhi(en[u].z, nb);
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) v[u] = tb[bk[u]];
-      uint32_t m[U];
-      uint32_t pend = 0;
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const uint32_t key = en[u].x;
-        const bool hx = v[u].x == key, hz = v[u].z == key;
-        m[u] = hx ? v[u].y : (hz ? v[u].w : 0u);
-        const bool more = !hx & !hz & (v[u].z != EMPTY_KEY) & (key != NO_KEY);
-        pend |= (uint32_t)more << u;
-      }
-      // a full bucket without the key: continue in the next buckets
-      while (pend) {
-        const int u = __builtin_ctz(pend);
-        const uint32_t key = en[0].x * (u == 0) + en[1].x * (u == 1) + en[2].x * (u == 2) + en[3].x * (u == 3);
-        uint32_t b = bk[0] * (u == 0) + bk[1] * (u == 1) + bk[2] * (u == 2) + bk[3] * (u == 3);
-        uint32_t got = 0;
-        while (true) {
-          b = b + 1 == nb ? 0 : b + 1;
-          const uint4 x = tb[b];
-          if (x.x == key) {
-            got = x.y;
-            break;
-          }
-          if (x.z == key) {
-            got = x.w;
-            break;
-          }
-          if (x.z == EMPTY_KEY) break;
-        }
-#pragma unroll
-        for (int uu = 0; uu < U; ++uu)
-          if (uu == u) m[uu] = got;
-        pend &= pend - 1;
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) acc += (uint64_t)(en[u].y < m[u] ? en[u].y : m[u]) << en[u].w;
+    for (int u = 0; u < 4; ++u) {
+      const int64_t c = c0 + 4 * threadIdx.x + u;
+      v[u] = c < n_cells ? D[c] : 0u;
+      t += v[u];
     }
-    for (int o = T; o < 64; o <<= 1) acc += __shfl_xor(acc, o, 64);
-    if (j0 == 0) keys[(q - q_begin) * n_docs + doc] = q_S[q] + Sd - 2 * acc;
+    const uint32_t incl = wave_incl_sum(t);
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    uint32_t before = carry;
+    for (int j = 0; j < w; ++j) before += wsum[j];
+    before += incl - t;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t c = c0 + 4 * threadIdx.x + u;
+      if (c < n_cells) D[c] = before;
+      before += v[u];
+    }
+    __syncthreads();
+    if (threadIdx.x == 1023) carry = before;
+    __syncthreads();
   }
+}
+
+// Wavefront per doc: place the doc's (doc in slice, mass) entries.  The
+// directory counters run from each list's start to its end, which is what
+// the query kernel reads.  Entry order inside a list is immaterial (integer
+// sums).
+__global__ __launch_bounds__(64) void k_post_fill(const int64_t* __restrict__ eoff, const uint32_t* __restrict__ ekey,
+                                                  const uint32_t* __restrict__ emass, int64_t n_docs, int64_t S,
+                                                  int64_t n_cells, const uint32_t* __restrict__ cbase,
+                                                  uint32_t* __restrict__ dir, uint2* __restrict__ post) {
+  for (int64_t d = blockIdx.x; d < n_docs; d += gridDim.x) {
+    const int64_t sl = d / S;
+    uint32_t* D = dir + sl * n_cells;
+    uint2* P = post + eoff[sl * S];
+    const uint32_t local = (uint32_t)(d - sl * S);
+    for (int64_t e = eoff[d] + lane_id(); e < eoff[d + 1]; e += 64) {
+      const uint32_t pos = atomicAdd(&D[cell_number(cbase, ekey[e])], 1u);
+      P[pos] = make_uint2(local, emass[e]);
+    }
+  }
+}
+
+// Workgroup per (query, slice).  Workgroups are dealt to the 8 XCDs in turn,
+// so block b runs on XCD b % 8; slices are given out so that each XCD walks
+// one slice at a time through all the queries of the launch, keeping that
+// slice's lists in its L2.
+__global__ __launch_bounds__(QP_THREADS) void k_qt_post(
+    const uint2* __restrict__ post, const uint32_t* __restrict__ dir, const uint32_t* __restrict__ cbase,
+    int64_t n_cells, int64_t S, int64_t n_sl, const int64_t* __restrict__ d_eoff, const uint64_t* __restrict__ d_S,
+    int64_t n_docs, const int64_t* __restrict__ q_eoff, const uint32_t* __restrict__ q_ekey,
+    const uint32_t* __restrict__ q_emass, const uint64_t* __restrict__ q_S, int64_t r0, int64_t n_rows, int B,
+    uint64_t* __restrict__ keys) {
+  __shared__ unsigned long long acc[QP_SLICE_MAX];
+  __shared__ uint4 items[QP_THREADS];
+  __shared__ uint32_t pstart[QP_THREADS];
+  __shared__ unsigned long long ctr;
+  const int64_t blk = blockIdx.x;
+  const int64_t local = blk >> 3;
+  const int64_t grp = local / n_rows, row = local - grp * n_rows;
+  const int64_t sl = grp * 8 + (blk & 7);
+  if (sl >= n_sl) return;
+  const int tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
+  const int64_t q = r0 + row, d0 = sl * S;
+  const int nd = (int)(n_docs - d0 < S ? n_docs - d0 : S);
+  for (int i = tid; i < nd; i += QP_THREADS) acc[i] = 0ull;
+  const uint32_t* D = dir + sl * n_cells;
+  const uint2* P = post + d_eoff[d0];
+  const int64_t e0 = q_eoff[q];
+  const int ne = (int)(q_eoff[q + 1] - e0);
+  for (int c0 = 0; c0 < ne; c0 += QP_THREADS) {
+    if (tid == 0) ctr = 0ull;
+    __syncthreads();
+    if (c0 + tid < ne) {
+      const uint32_t key = q_ekey[e0 + c0 + tid];
+      const uint32_t c = cell_number(cbase, key);
+      const uint32_t o1 = D[c], o0 = c ? D[c - 1] : 0u;
+      if (o1 > o0) {
+        const uint32_t len = o1 - o0, np = (len + QP_PIECE - 1) / QP_PIECE;
+        const unsigned long long old = atomicAdd(&ctr, (1ull << 32) | np);
+        const uint32_t idx = (uint32_t)(old >> 32);
+        items[idx] = make_uint4(o0, len, q_emass[e0 + c0 + tid], (uint32_t)B - (key >> KEY_DEPTH_SHIFT));
+        pstart[idx] = (uint32_t)old;  // pieces before this list: increasing with idx
+      }
+    }
+    __syncthreads();
+    const unsigned long long cc = ctr;
+    const uint32_t n_items = (uint32_t)(cc >> 32), n_pieces = (uint32_t)cc;
+    for (uint32_t p = w; p < n_pieces; p += QP_WAVES) {
+      uint32_t lo = 0, hi = n_items - 1;  // last list whose first piece is <= p
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (pstart[mid] <= p) lo = mid;
+        else hi = mid - 1;
+      }
+      const uint4 it = items[lo];
+      const uint32_t off = (p - pstart[lo]) * QP_PIECE;
+      const uint32_t n = min((uint32_t)QP_PIECE, it.y - off);
+      const uint2* src = P + it.x + off;
+#pragma unroll
+      for (int u = 0; u < QP_PIECE / 64; ++u) {
+        const uint32_t j = u * 64 + lane;
+        if (j < n) {
+          const uint2 e = src[j];
+          atomicAdd(&acc[e.x], (unsigned long long)min(it.z, e.y) << it.w);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  const uint64_t Sq = q_S[q];
+  uint64_t* out = keys + row * n_docs + d0;
+  const uint64_t* Sd = d_S + d0;
+  for (int i = tid; i < nd; i += QP_THREADS) out[i] = Sq + Sd[i] - 2ull * acc[i];
 }
 
 // Explicit (query, doc) pairs: one wavefront per pair, the query table in LDS.
@@ -304,39 +327,31 @@ void check_indices(ft_index* ix, const int64_t* v, int64_t n, int64_t bound, hip
 
 constexpr int SLOTS_SMALL = 4096, SLOTS_LARGE = 8192;
 
-// Doc tables and tiles for ranking all docs, made once per index: table
-// sizes from the embedding sizes, tables built on the device, tiles of up to
-// 32 consecutive docs whose tables fit QT_BUCKETS.
-static void prepare_doc_tables(ft_index* ix, hipStream_t s) {
-  if (ix->doc_tiles_small > 0) return;
+// Inverted doc lists for ranking all docs, made once per index.
+static void prepare_postings(ft_index* ix, hipStream_t s) {
+  if (ix->post_nsl > 0) return;
   const int64_t n = ix->docs.n;
-  std::vector<int64_t> eoff(n + 1), tb(n + 1);
-  FT_HIP(hipMemcpyAsync(eoff.data(), ix->docs.ecnt.p, (n + 1) * 8, hipMemcpyDeviceToHost, s));
-  FT_HIP(hipStreamSynchronize(s));
-  tb[0] = 0;
-  for (int64_t d = 0; d < n; ++d) {
-    const int64_t nb = std::max<int64_t>(2, eoff[d + 1] - eoff[d]);
-    FT_REQUIRE(nb <= QT_BUCKETS, FT_ERANGE, "a dataset distribution touches more than 4096 tree cells");
-    tb[d + 1] = tb[d] + nb;
-  }
-  std::vector<DocTile> tiles;
-  int64_t d = 0;
-  while (d < n) {
-    int T = 1;
-    while (T * 2 <= 32 && d + 2 * T <= n && tb[d + 2 * T] - tb[d] <= QT_BUCKETS) T *= 2;
-    tiles.push_back(DocTile{d, T, 0});
-    d += T;
-  }
-  int64_t* dtb = (int64_t*)ix->doc_tb_off.ensure((n + 1) * 8);
-  FT_HIP(hipMemcpyAsync(dtb, tb.data(), (n + 1) * 8, hipMemcpyHostToDevice, s));
-  uint4* tables = (uint4*)ix->doc_tables.ensure(tb[n] * sizeof(uint4));
-  k_build_doc_tables<<<(unsigned)n, 64, 0, s>>>(ix->docs.ecnt.as<int64_t>(), ix->docs.ekey.as<uint32_t>(),
-                                                ix->docs.emass.as<uint32_t>(), dtb, n, tables);
+  const int64_t S = post_slice_size(n), n_sl = ceil_div(n, S);
+  const int64_t n_cells = std::max<int64_t>(1, ix->n_nodes - 1);
+  FT_REQUIRE(n_sl * n_cells <= (int64_t(1) << 32), FT_ERANGE,
+             "the inverted Quadtree lists would need more than 16 GiB of directory");
+  uint32_t cb[32] = {0};
+  for (int k = 2; k <= ix->height; ++k) cb[k] = cb[k - 1] + (uint32_t)ix->depth_nodes[k - 1];
+  uint32_t* cbase = (uint32_t*)ix->post_cbase.ensure(sizeof(cb));
+  FT_HIP(hipMemcpyAsync(cbase, cb, sizeof(cb), hipMemcpyHostToDevice, s));
+  uint32_t* dir = (uint32_t*)ix->post_dir.ensure(n_sl * n_cells * 4);
+  FT_HIP(hipMemsetAsync(dir, 0, n_sl * n_cells * 4, s));
+  uint2* post = (uint2*)ix->post.ensure(std::max<int64_t>(1, ix->docs.emb_nnz) * sizeof(uint2));
+  const unsigned g = (unsigned)std::min<int64_t>(n, 1 << 20);
+  k_post_count<<<g, 64, 0, s>>>(ix->docs.ecnt.as<int64_t>(), ix->docs.ekey.as<uint32_t>(), n, S, n_cells, cbase, dir);
+  k_post_scan<<<(unsigned)n_sl, 1024, 0, s>>>(dir, n_cells);
+  k_post_fill<<<g, 64, 0, s>>>(ix->docs.ecnt.as<int64_t>(), ix->docs.ekey.as<uint32_t>(),
+                               ix->docs.emass.as<uint32_t>(), n, S, n_cells, cbase, dir, post);
   FT_HIP(hipGetLastError());
-  DocTile* dt = (DocTile*)ix->doc_tiles.ensure(tiles.size() * sizeof(DocTile));
-  FT_HIP(hipMemcpyAsync(dt, tiles.data(), tiles.size() * sizeof(DocTile), hipMemcpyHostToDevice, s));
   FT_HIP(hipStreamSynchronize(s));
-  ix->doc_tiles_small = (int64_t)tiles.size();
+  ix->post_slice = S;
+  ix->post_cells = n_cells;
+  ix->post_nsl = n_sl;
 }
 
 }  // namespace ft
@@ -359,33 +374,25 @@ extern "C" ft_status ft_quadtree_knn(ft_index* ix, const int64_t* q_off, const u
     std::vector<int64_t> eoff(n_q + 1);
     FT_HIP(hipMemcpyAsync(eoff.data(), ix->qry.ecnt.p, (n_q + 1) * 8, hipMemcpyDeviceToHost, s));
     FT_HIP(hipStreamSynchronize(s));
-    for (int64_t q = 0; q < n_q; ++q)
-      FT_REQUIRE(eoff[q + 1] - eoff[q] <= SLOTS_LARGE / 2, FT_ERANGE,
-                 "a query touches more than 4096 tree cells");
+    if (cand)
+      for (int64_t q = 0; q < n_q; ++q)
+        FT_REQUIRE(eoff[q + 1] - eoff[q] <= SLOTS_LARGE / 2, FT_ERANGE,
+                   "with candidate lists, a query may touch at most 4096 tree cells");
     // query chunks bound the key buffer to about 4 GiB
     const int64_t rows_per_chunk = std::max<int64_t>(1, std::min<int64_t>(n_q, (int64_t(1) << 29) / n_cols));
     uint64_t* keys = (uint64_t*)ix->ws_keys.ensure(rows_per_chunk * n_cols * 8);
-    uint4* q_ent = nullptr;
-    if (!cand) {
-      prepare_doc_tables(ix, s);
-      // padded by the furthest a lookup group can reach past a query's end
-      q_ent = (uint4*)ix->ws_misc.ensure((ix->qry.emb_nnz + 4 * 64) * sizeof(uint4));
-      FT_HIP(hipMemsetAsync(q_ent + ix->qry.emb_nnz, 0, 4 * 64 * sizeof(uint4), s));
-      if (ix->qry.emb_nnz > 0)
-        k_stage_query_entries<<<(unsigned)ceil_div(ix->qry.emb_nnz, 256), 256, 0, s>>>(
-            ix->qry.ekey.as<uint32_t>(), ix->qry.emass.as<uint32_t>(), ix->qry.emb_nnz, ix->B, q_ent);
-      FT_HIP(hipGetLastError());
-    }
+    if (!cand) prepare_postings(ix, s);
     for (int64_t r0 = 0; r0 < n_q; r0 += rows_per_chunk) {
       const int64_t r1 = std::min(n_q, r0 + rows_per_chunk);
       if (!cand) {
-        // all docs: doc tables in LDS, queries streamed
-        const int64_t qpb = 256;
-        const unsigned gy = (unsigned)ceil_div(r1 - r0, qpb);
-        k_qt_doctile<<<dim3((unsigned)ix->doc_tiles_small, gy), QT_TILE_THREADS, 0, s>>>(
-            ix->doc_tiles.as<DocTile>(), ix->doc_tables.as<uint4>(), ix->doc_tb_off.as<int64_t>(),
-            ix->docs.S.as<uint64_t>(), ix->qry.ecnt.as<int64_t>(), q_ent, ix->qry.S.as<uint64_t>(), r0, r1, qpb,
-            n_cols, keys);
+        // all docs: the inverted lists, one workgroup per (query, slice)
+        const int64_t rows = r1 - r0, groups = ceil_div(ix->post_nsl, 8);
+        FT_REQUIRE(groups * 8 * rows < (int64_t(1) << 31), FT_ERANGE, "too many (query, slice) workgroups");
+        k_qt_post<<<(unsigned)(groups * 8 * rows), QP_THREADS, 0, s>>>(
+            ix->post.as<uint2>(), ix->post_dir.as<uint32_t>(), ix->post_cbase.as<uint32_t>(), ix->post_cells,
+            ix->post_slice, ix->post_nsl, ix->docs.ecnt.as<int64_t>(), ix->docs.S.as<uint64_t>(), n_cols,
+            ix->qry.ecnt.as<int64_t>(), ix->qry.ekey.as<uint32_t>(), ix->qry.emass.as<uint32_t>(),
+            ix->qry.S.as<uint64_t>(), r0, rows, ix->B, keys);
         FT_HIP(hipGetLastError());
       } else {
         // candidate lists: one query per workgroup, its table in LDS
