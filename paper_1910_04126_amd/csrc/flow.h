@@ -25,6 +25,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "common.h"
 #include "wave.h"
@@ -260,48 +261,81 @@ __device__ int flow_match(FlowLds<C>& L, const int nq, const int nd, const uint8
 }
 
 // Euclidean price of the matches: sum eta * ||x_doc - x_query||_2 (float32
-// distances, float64 accumulation).  G lanes share one match; rows are
-// read as float4 when VEC == 4.
+// distances, float64 accumulation).  G lanes share one match, and a lane
+// reads up to PV float4 (or floats when VEC == 1) of each row per pass: all
+// loads of U consecutive match groups are issued before any is used, so a
+// wavefront keeps 64 / G * U matches in flight.  The summation order is
+// fixed, so costs do not depend on the schedule.
 template <int C, int G, int VEC>
 __device__ double flow_price(const FlowLds<C>& L, const int E, const float* __restrict__ X,
                              const uint32_t* __restrict__ row_of_rank, const int stride, const int d) {
+  constexpr int PER = 64 / G;
+  constexpr int PV = C >= 8 ? 8 : 2;
+  constexpr int U = 1;
+  using V4 = typename std::conditional<VEC == 4, float4, float>::type;
   const int lane = lane_id();
   const int g = lane / G, sub = lane % G;
-  constexpr int PER = 64 / G;
+  const int nv = VEC == 4 ? stride >> 2 : d;
   double cost = 0.0;
-  for (int e0 = 0; e0 < E; e0 += PER) {
-    const int e = e0 + g;
-    float acc = 0.0f;
-    uint32_t eta = 0;
-    if (e < E) {
-      const uint32_t pos = L.em_pos[e];
-      const uint32_t rd = L.rank[pos & 0xFFFFu], rq = L.rank[pos >> 16];
-      eta = L.em_eta[e];
-      if (rd != rq) {
+  for (int e0 = 0; e0 < E; e0 += PER * U) {
+    const V4* pa[U];
+    const V4* pb[U];
+    uint32_t eta[U];
+    bool live[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * PER + g;
+      eta[u] = 0;
+      live[u] = false;
+      pa[u] = pb[u] = nullptr;
+      if (e < E) {
+        const uint32_t pos = L.em_pos[e];
+        const uint32_t rd = L.rank[pos & 0xFFFFu], rq = L.rank[pos >> 16];
+        eta[u] = L.em_eta[e];
+        live[u] = rd != rq;
         const int64_t rowd = row_of_rank ? row_of_rank[rd] : rd;
         const int64_t rowq = row_of_rank ? row_of_rank[rq] : rq;
-        const float* xd = X + rowd * stride;
-        const float* xq = X + rowq * stride;
-        if (VEC == 4) {
-          const float4* a4 = reinterpret_cast<const float4*>(xd);
-          const float4* b4 = reinterpret_cast<const float4*>(xq);
-          const int nv = stride >> 2;
-          for (int v = sub; v < nv; v += G) {
-            const float4 a = a4[v], b = b4[v];
-            const float dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z, dw = a.w - b.w;
-            acc += dx * dx + dy * dy + dz * dz + dw * dw;
-          }
-        } else {
-          for (int v = sub; v < d; v += G) {
-            const float dx = xd[v] - xq[v];
-            acc += dx * dx;
-          }
-        }
+        pa[u] = reinterpret_cast<const V4*>(X + rowd * stride);
+        pb[u] = reinterpret_cast<const V4*>(X + rowq * stride);
       }
     }
+    float acc[U];
 #pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-    if (sub == 0 && e < E) cost += (double)eta * (double)sqrtf(acc);
+    for (int u = 0; u < U; ++u) acc[u] = 0.0f;
+    for (int v0 = 0; v0 < nv; v0 += G * PV) {
+      V4 a[U][PV], b[U][PV];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int t = 0; t < PV; ++t) {
+          const int v = v0 + t * G + sub;
+          if (live[u] && v < nv) {
+            a[u][t] = pa[u][v];
+            b[u][t] = pb[u][v];
+          } else {
+            a[u][t] = b[u][t] = V4{};
+          }
+        }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int t = 0; t < PV; ++t) {
+          if constexpr (VEC == 4) {
+            const float dx = a[u][t].x - b[u][t].x, dy = a[u][t].y - b[u][t].y;
+            const float dz = a[u][t].z - b[u][t].z, dw = a[u][t].w - b[u][t].w;
+            acc[u] += dx * dx + dy * dy + dz * dz + dw * dw;
+          } else {
+            const float dx = a[u][t] - b[u][t];
+            acc[u] += dx * dx;
+          }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+      for (int o = G / 2; o > 0; o >>= 1) acc[u] += __shfl_xor(acc[u], o, 64);
+      if (sub == 0 && live[u]) cost += (double)eta[u] * (double)sqrtf(acc[u]);
+    }
   }
   return wave_sum(cost);
 }
