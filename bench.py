@@ -12,7 +12,9 @@ The plain one-launch-per-query Flowtree stage is timed on the same
 candidates afterwards and reported beside it.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload batched|text|image]
-       [--no-cpu-baseline]
+       [--no-cpu-baseline] [--no-plain]
+       python bench.py --calibrate-copy BYTES   (a plain device copy of BYTES, five times: the
+                                                 reference for the HBM byte counters)
 """
 from __future__ import annotations
 
@@ -58,7 +60,10 @@ def main():
     ap.add_argument("--workload", default="batched")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0)
     args = ap.parse_args()
+    if args.calibrate_copy:
+        return calibrate_copy(args.calibrate_copy)
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs on a single MI355X "
               "(the multi-GPU sharding is a design note, not built)", file=sys.stderr)
@@ -191,6 +196,21 @@ def main():
         "index": info,
     }
     print(json.dumps(out), flush=True)
+
+
+def calibrate_copy(nbytes):
+    """Copy a device buffer of nbytes five times (one copy kernel each), so
+    the counters' FETCH_SIZE / WRITE_SIZE per dispatch can be compared with
+    the nbytes actually moved."""
+    import torch
+    dev = torch.device("cuda:0")
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "copies": 5}), flush=True)
 
 
 def cpu_baseline(ds, prune, k, n_cols):

@@ -18,8 +18,11 @@
 // Only depths that occur among the adjacent LCA depths (plus the root) can
 // change anything; the others are skipped.
 //
-// Layout: a wavefront owns NMAX = 64 * C merged items, lane l the items
-// [l*C, l*C + C); per-item state lives in LDS.
+// Layout: a workgroup of W wavefronts owns NMAX = 64 * W * C merged items,
+// thread t the items [t*C, t*C + C); per-item state lives in LDS.  Scans run
+// per wavefront with DPP/shuffles, and their carries cross wavefronts through
+// one LDS slot per wavefront, so large pairs spread over several wavefronts
+// instead of crowding one.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -32,9 +35,10 @@
 
 namespace ft {
 
-template <int C>
+template <int C, int W = 1>
 struct FlowLds {
-  static constexpr int N = 64 * C;
+  static constexpr int N = 64 * C * W;
+  int64_t work;        // persistent kernels: the grabbed chunk, broadcast
   uint32_t rank[N];    // merged Morton ranks
   uint32_t res[N];     // unmatched mass
   uint32_t pp[N];      // doc-side inclusive prefix (before the merge: input ranks)
@@ -43,6 +47,9 @@ struct FlowLds {
   uint32_t em_eta[N];  // match: integer mass moved
   uint16_t slot[N];    // merged position -> input slot (query [0, nq), doc [nq, nq + nd))
   int8_t lcn[N];       // LCA depth of (t, t + 1); -1 after the last item
+  // one slot per wavefront for cross-wavefront scan carries
+  uint32_t x_p[W], x_n[W], x_f[W], x_c[W], x_m[W];
+  int32_t x_s[W], x_e[W];
 };
 
 // Where a saved flow goes (gradient and inspection paths).
@@ -55,17 +62,17 @@ struct FlowSave {
 };
 
 // Stage a pair: query items into slots [0, nq), doc items into [nq, nq + nd).
-template <int C>
-__device__ __forceinline__ void flow_stage(FlowLds<C>& L, const uint32_t* __restrict__ qr,
+template <int C, int W>
+__device__ __forceinline__ void flow_stage(FlowLds<C, W>& L, const uint32_t* __restrict__ qr,
                                            const uint32_t* __restrict__ qm, int nq,
                                            const uint32_t* __restrict__ dr,
                                            const uint32_t* __restrict__ dm, int nd) {
-  const int lane = lane_id();
-  for (int i = lane; i < nq; i += 64) {
+  const int tid = threadIdx.x;
+  for (int i = tid; i < nq; i += 64 * W) {
     L.pp[i] = qr[i];
     L.pn[i] = qm[i];
   }
-  for (int i = lane; i < nd; i += 64) {
+  for (int i = tid; i < nd; i += 64 * W) {
     L.pp[nq + i] = dr[i];
     L.pn[nq + i] = dm[i];
   }
@@ -73,13 +80,13 @@ __device__ __forceinline__ void flow_stage(FlowLds<C>& L, const uint32_t* __rest
 }
 
 // The greedy flow of a staged pair; returns the number of matches in
-// L.em_pos / L.em_eta (uniform across the wavefront).
-template <int C, bool SAVE>
-__device__ int flow_match(FlowLds<C>& L, const int nq, const int nd, const uint8_t* __restrict__ st,
+// L.em_pos / L.em_eta (uniform across the workgroup).
+template <int C, int W, bool SAVE>
+__device__ int flow_match(FlowLds<C, W>& L, const int nq, const int nd, const uint8_t* __restrict__ st,
                           const int64_t V, const int B, FlowSave sv, uint32_t* __restrict__ status) {
-  const int lane = lane_id();
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int n = nq + nd;
-  const int t0 = lane * C;
+  const int t0 = tid * C;
   // ---- merge both supports by rank (doc first on equal ranks)
   {
     const uint32_t* qr = L.pp;
@@ -120,6 +127,11 @@ __device__ int flow_match(FlowLds<C>& L, const int nq, const int nd, const uint8
     }
   }
   mask = wave_or(mask);
+  if (W > 1) {
+    if (lane == 0) L.x_m[w] = mask;
+    __syncthreads();
+    for (int j = 0; j < W; ++j) mask |= L.x_m[j];
+  }
   __syncthreads();
   int E = 0;
   while (mask) {
@@ -142,15 +154,44 @@ __device__ int flow_match(FlowLds<C>& L, const int nq, const int nd, const uint8
       }
     }
     uint32_t tp = run_p, tn = run_n;
-    wave_seg_incl_sum2(tp, tn, last_start >= 0);
-    uint32_t cp = __shfl_up(tp, 1, 64), cn = __shfl_up(tn, 1, 64);
-    int prev_start = __shfl_up(wave_incl_max(last_start), 1, 64);
-    int next_end = __shfl_down(wave_suffix_min(first_end), 1, 64);
-    if (lane == 0) {
-      cp = cn = 0;
-      prev_start = 0;
+    const bool has = wave_seg_incl_sum2(tp, tn, last_start >= 0);
+    const int ls_incl = wave_incl_max(last_start);
+    const int fe_suf = wave_suffix_min(first_end);
+    // carries from the other wavefronts: the segmented sums reaching this
+    // wavefront's first lane, the latest segment start before it, and the
+    // earliest segment end after it
+    uint32_t kp = 0, kn = 0;
+    int ks = 0, ke = 0x7FFFFFFF;
+    if (W > 1) {
+      if (lane == 63) {
+        L.x_p[w] = tp;
+        L.x_n[w] = tn;
+        L.x_f[w] = has ? 1u : 0u;
+        L.x_s[w] = ls_incl;
+      }
+      if (lane == 0) L.x_e[w] = fe_suf;
+      __syncthreads();
+      for (int j = w - 1; j >= 0; --j) {
+        kp += L.x_p[j];
+        kn += L.x_n[j];
+        if (L.x_f[j]) break;
+      }
+      for (int j = 0; j < w; ++j) ks = max(ks, L.x_s[j]);
+      for (int j = w + 1; j < W; ++j) ke = min(ke, L.x_e[j]);
+      if (!has) {
+        tp += kp;
+        tn += kn;
+      }
     }
-    if (lane == 63) next_end = 0x7FFFFFFF;
+    uint32_t cp = __shfl_up(tp, 1, 64), cn = __shfl_up(tn, 1, 64);
+    int prev_start = max(ks, __shfl_up(ls_incl, 1, 64));
+    int next_end = min(ke, __shfl_down(fe_suf, 1, 64));
+    if (lane == 0) {
+      cp = kp;
+      cn = kn;
+      prev_start = ks;
+    }
+    if (lane == 63) next_end = ke;
     // inclusive prefixes with the carry from earlier lanes; segment bounds
     uint32_t se[C];
     run_p = cp;
@@ -232,8 +273,19 @@ __device__ int flow_match(FlowLds<C>& L, const int nq, const int nd, const uint8
       }
     }
     const int incl = wave_incl_sum(cnt);
-    int off = E + incl - cnt;
-    const int total = __shfl(incl, 63, 64);
+    int before = 0, total;
+    if (W > 1) {
+      if (lane == 63) L.x_c[w] = (uint32_t)incl;
+      __syncthreads();
+      total = 0;
+      for (int j = 0; j < W; ++j) {
+        if (j < w) before += (int)L.x_c[j];
+        total += (int)L.x_c[j];
+      }
+    } else {
+      total = __shfl(incl, 63, 64);
+    }
+    int off = E + before + incl - cnt;
     for (int c = 0; c < C; ++c) {
       if (m_eta[c]) {
         L.em_pos[off] = m_pos[c];
@@ -262,82 +314,77 @@ __device__ int flow_match(FlowLds<C>& L, const int nq, const int nd, const uint8
 
 // Euclidean price of the matches: sum eta * ||x_doc - x_query||_2 (float32
 // distances, float64 accumulation).  G lanes share one match, and a lane
-// reads up to PV float4 (or floats when VEC == 1) of each row per pass: all
-// loads of U consecutive match groups are issued before any is used, so a
-// wavefront keeps 64 / G * U matches in flight.  The summation order is
-// fixed, so costs do not depend on the schedule.
-template <int C, int G, int VEC>
-__device__ double flow_price(const FlowLds<C>& L, const int E, const float* __restrict__ X,
+// reads up to PV float4 (or floats when VEC == 1) of each row per pass, all
+// issued before any is used.  Each match's product lands in LDS (over the
+// prefix arrays, free by now) and wavefront 0 adds them up in one fixed
+// order, so a cost does not depend on W or on the schedule.  The result is
+// valid in wavefront 0.
+template <int C, int W, int G, int VEC>
+__device__ double flow_price(FlowLds<C, W>& L, const int E, const float* __restrict__ X,
                              const uint32_t* __restrict__ row_of_rank, const int stride, const int d) {
-  constexpr int PER = 64 / G;
-  constexpr int PV = C >= 8 ? 8 : 2;
-  constexpr int U = 1;
+  constexpr int PER = 64 * W / G;
+  constexpr int PV = C * W >= 8 ? 5 : 2;
   using V4 = typename std::conditional<VEC == 4, float4, float>::type;
-  const int lane = lane_id();
-  const int g = lane / G, sub = lane % G;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int g = tid / G, sub = tid % G;
   const int nv = VEC == 4 ? stride >> 2 : d;
-  double cost = 0.0;
-  for (int e0 = 0; e0 < E; e0 += PER * U) {
-    const V4* pa[U];
-    const V4* pb[U];
-    uint32_t eta[U];
-    bool live[U];
+  double* prod = reinterpret_cast<double*>(L.pp);  // pp and pn are contiguous: 8 * N bytes
+  for (int e0 = 0; e0 < E; e0 += PER) {
+    const int e = e0 + g;
+    const V4* pa = nullptr;
+    const V4* pb = nullptr;
+    uint32_t eta = 0;
+    bool live = false;
+    if (e < E) {
+      const uint32_t pos = L.em_pos[e];
+      const uint32_t rd = L.rank[pos & 0xFFFFu], rq = L.rank[pos >> 16];
+      eta = L.em_eta[e];
+      live = rd != rq;
+      const int64_t rowd = row_of_rank ? row_of_rank[rd] : rd;
+      const int64_t rowq = row_of_rank ? row_of_rank[rq] : rq;
+      pa = reinterpret_cast<const V4*>(X + rowd * stride);
+      pb = reinterpret_cast<const V4*>(X + rowq * stride);
+    }
+    float acc = 0.0f;
+    for (int v0 = 0; v0 < nv; v0 += G * PV) {
+      V4 a[PV], b[PV];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int e = e0 + u * PER + g;
-      eta[u] = 0;
-      live[u] = false;
-      pa[u] = pb[u] = nullptr;
-      if (e < E) {
-        const uint32_t pos = L.em_pos[e];
-        const uint32_t rd = L.rank[pos & 0xFFFFu], rq = L.rank[pos >> 16];
-        eta[u] = L.em_eta[e];
-        live[u] = rd != rq;
-        const int64_t rowd = row_of_rank ? row_of_rank[rd] : rd;
-        const int64_t rowq = row_of_rank ? row_of_rank[rq] : rq;
-        pa[u] = reinterpret_cast<const V4*>(X + rowd * stride);
-        pb[u] = reinterpret_cast<const V4*>(X + rowq * stride);
+      for (int t = 0; t < PV; ++t) {
+        const int v = v0 + t * G + sub;
+        if (live && v < nv) {
+          a[t] = pa[v];
+          b[t] = pb[v];
+        } else {
+          a[t] = b[t] = V4{};
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < PV; ++t) {
+        if constexpr (VEC == 4) {
+          const float dx = a[t].x - b[t].x, dy = a[t].y - b[t].y;
+          const float dz = a[t].z - b[t].z, dw = a[t].w - b[t].w;
+          acc += dx * dx + dy * dy + dz * dz + dw * dw;
+        } else {
+          const float dx = a[t] - b[t];
+          acc += dx * dx;
+        }
       }
     }
-    float acc[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) acc[u] = 0.0f;
-    for (int v0 = 0; v0 < nv; v0 += G * PV) {
-      V4 a[U][PV], b[U][PV];
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-#pragma unroll
-        for (int t = 0; t < PV; ++t) {
-          const int v = v0 + t * G + sub;
-          if (live[u] && v < nv) {
-            a[u][t] = pa[u][v];
-            b[u][t] = pb[u][v];
-          } else {
-            a[u][t] = b[u][t] = V4{};
-          }
-        }
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-#pragma unroll
-        for (int t = 0; t < PV; ++t) {
-          if constexpr (VEC == 4) {
-            const float dx = a[u][t].x - b[u][t].x, dy = a[u][t].y - b[u][t].y;
-            const float dz = a[u][t].z - b[u][t].z, dw = a[u][t].w - b[u][t].w;
-            acc[u] += dx * dx + dy * dy + dz * dz + dw * dw;
-          } else {
-            const float dx = a[u][t] - b[u][t];
-            acc[u] += dx * dx;
-          }
-        }
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-#pragma unroll
-      for (int o = G / 2; o > 0; o >>= 1) acc[u] += __shfl_xor(acc[u], o, 64);
-      if (sub == 0 && live[u]) cost += (double)eta[u] * (double)sqrtf(acc[u]);
-    }
+    for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (sub == 0 && e < E) prod[e] = live ? (double)eta * (double)sqrtf(acc) : 0.0;
   }
-  return wave_sum(cost);
+  __syncthreads();
+  double cost = 0.0;
+  if (tid < 64) {
+    // the order of one wavefront pricing alone: group g adds matches
+    // g, g + 64/G, ... in turn, then the groups are summed by butterfly
+    constexpr int PER1 = 64 / G;
+    if (lane % G == 0)
+      for (int e = lane / G; e < E; e += PER1) cost += prod[e];
+    cost = wave_sum(cost);
+  }
+  return cost;
 }
 
 // Lanes per match from the row length in float4 units.
@@ -347,13 +394,15 @@ inline int lanes_for(int nvec) {
   return g;
 }
 
-// Merged-item capacity classes: NMAX = 64 * C.
+// Merged-item capacity classes: NMAX = 64 * W * C items on W wavefronts of C
+// items per lane (128, 256, 512, 1024, 2048).
 constexpr int N_CLASSES = 5;
-constexpr int CLASS_C[N_CLASSES] = {2, 4, 8, 16, 32};
+constexpr int CLASS_C[N_CLASSES] = {2, 4, 4, 4, 8};
+constexpr int CLASS_W[N_CLASSES] = {1, 1, 2, 4, 4};
 
 inline int class_for(int n) {
   for (int i = 0; i < N_CLASSES; ++i)
-    if (n <= 64 * CLASS_C[i]) return i;
+    if (n <= 64 * CLASS_W[i] * CLASS_C[i]) return i;
   return -1;
 }
 

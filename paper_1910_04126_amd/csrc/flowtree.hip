@@ -10,6 +10,7 @@
 #include <fstream>
 #include <functional>
 #include <sstream>
+#include <type_traits>
 #include <vector>
 
 #include "common.h"
@@ -37,46 +38,47 @@ struct PairArgs {
   float* cost;  // [n_q * n_cols]
 };
 
-template <int C, int G>
-__device__ __forceinline__ void flow_one(FlowLds<C>& L, const PairArgs& a, const int64_t p) {
+template <int C, int W, int G>
+__device__ __forceinline__ void flow_one(FlowLds<C, W>& L, const PairArgs& a, const int64_t p) {
   const int64_t q = p / a.n_cols;
   const int64_t c = p - q * a.n_cols;
   const int64_t doc = a.cand ? a.cand[p] : c;
   const int64_t qa = a.q_off[q], da = a.d_off[doc];
   const int nq = (int)(a.q_off[q + 1] - qa), nd = (int)(a.d_off[doc + 1] - da);
-  if (nq + nd > FlowLds<C>::N) {  // the host sizes C; never taken
+  if (nq + nd > FlowLds<C, W>::N) {  // the host sizes the class; never taken
     if (threadIdx.x == 0) atomicOr(a.status, ERR_FLOW);
     return;
   }
   flow_stage(L, a.q_rank + qa, a.q_mass + qa, nq, a.d_rank + da, a.d_mass + da, nd);
-  const int E = flow_match<C, false>(L, nq, nd, a.st, a.V, a.B, FlowSave{}, a.status);
-  const double cost = flow_price<C, G, 4>(L, E, a.X, nullptr, a.stride, a.stride);
+  const int E = flow_match<C, W, false>(L, nq, nd, a.st, a.V, a.B, FlowSave{}, a.status);
+  const double cost = flow_price<C, W, G, 4>(L, E, a.X, nullptr, a.stride, a.stride);
   if (threadIdx.x == 0) a.cost[p] = (float)ldexp(cost, -a.Q);
   __syncthreads();
 }
 
-// Plain: block b handles column b of query q.
-template <int C, int G>
-__global__ __launch_bounds__(64) void k_flow_plain(PairArgs a, int64_t q) {
-  __shared__ FlowLds<C> L;
-  flow_one<C, G>(L, a, q * a.n_cols + blockIdx.x);
+// Plain: workgroup b handles column b of query q.
+template <int C, int W, int G>
+__global__ __launch_bounds__(64 * W) void k_flow_plain(PairArgs a, int64_t q) {
+  __shared__ FlowLds<C, W> L;
+  flow_one<C, W, G>(L, a, q * a.n_cols + blockIdx.x);
 }
 
-// Persistent: waves grab chunks of the class's pair list until it is used up.
-template <int C, int G>
-__global__ __launch_bounds__(64) void k_flow_persistent(PairArgs a, const int64_t* __restrict__ list,
-                                                        const int64_t* __restrict__ offsets, int64_t n_q, int cls,
-                                                        uint32_t* __restrict__ counters, int chunk) {
-  __shared__ FlowLds<C> L;
+// Persistent: workgroups grab chunks of the class's pair list until it is
+// used up.
+template <int C, int W, int G>
+__global__ __launch_bounds__(64 * W) void k_flow_persistent(PairArgs a, const int64_t* __restrict__ list,
+                                                            const int64_t* __restrict__ offsets, int64_t n_q, int cls,
+                                                            uint32_t* __restrict__ counters, int chunk) {
+  __shared__ FlowLds<C, W> L;
   const int64_t begin = offsets[(int64_t)cls * n_q], end = offsets[(int64_t)(cls + 1) * n_q];
   while (true) {
-    uint32_t w = 0;
-    if (threadIdx.x == 0) w = atomicAdd(&counters[cls], 1u);
-    w = __shfl(w, 0, 64);
-    const int64_t i0 = begin + (int64_t)w * chunk;
+    if (threadIdx.x == 0) L.work = (int64_t)atomicAdd(&counters[cls], 1u);
+    __syncthreads();
+    const int64_t i0 = begin + L.work * chunk;
+    __syncthreads();  // everyone has read the grab before thread 0 makes the next
     if (i0 >= end) break;
     const int64_t i1 = min(end, i0 + chunk);
-    for (int64_t i = i0; i < i1; ++i) flow_one<C, G>(L, a, list[i]);
+    for (int64_t i = i0; i < i1; ++i) flow_one<C, W, G>(L, a, list[i]);
   }
 }
 
@@ -127,73 +129,58 @@ __global__ __launch_bounds__(64) void k_bucket_scatter(PairArgs a, int64_t n_q, 
 
 // ------------------------------------------------------------ dispatch --
 
-template <int C>
-static void launch_plain_c(int G, const PairArgs& a, int64_t q, hipStream_t s) {
-  dim3 grid((unsigned)a.n_cols);
+// Calls f(integral_constant C, integral_constant W) for a size class.
+template <class F>
+static void with_class(int cls, F&& f) {
+  switch (cls) {
+    case 0: f(std::integral_constant<int, CLASS_C[0]>{}, std::integral_constant<int, CLASS_W[0]>{}); break;
+    case 1: f(std::integral_constant<int, CLASS_C[1]>{}, std::integral_constant<int, CLASS_W[1]>{}); break;
+    case 2: f(std::integral_constant<int, CLASS_C[2]>{}, std::integral_constant<int, CLASS_W[2]>{}); break;
+    case 3: f(std::integral_constant<int, CLASS_C[3]>{}, std::integral_constant<int, CLASS_W[3]>{}); break;
+    default: f(std::integral_constant<int, CLASS_C[4]>{}, std::integral_constant<int, CLASS_W[4]>{}); break;
+  }
+}
+
+// Calls f(integral_constant G) for the lanes per match.
+template <class F>
+static void with_lanes(int G, F&& f) {
   switch (G) {
-    case 1: k_flow_plain<C, 1><<<grid, 64, 0, s>>>(a, q); break;
-    case 2: k_flow_plain<C, 2><<<grid, 64, 0, s>>>(a, q); break;
-    case 4: k_flow_plain<C, 4><<<grid, 64, 0, s>>>(a, q); break;
-    case 8: k_flow_plain<C, 8><<<grid, 64, 0, s>>>(a, q); break;
-    default: k_flow_plain<C, 16><<<grid, 64, 0, s>>>(a, q); break;
+    case 1: f(std::integral_constant<int, 1>{}); break;
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    case 8: f(std::integral_constant<int, 8>{}); break;
+    default: f(std::integral_constant<int, 16>{}); break;
   }
 }
 
 static void launch_plain(int cls, int G, const PairArgs& a, int64_t q, hipStream_t s) {
-  switch (cls) {
-    case 0: launch_plain_c<2>(G, a, q, s); break;
-    case 1: launch_plain_c<4>(G, a, q, s); break;
-    case 2: launch_plain_c<8>(G, a, q, s); break;
-    case 3: launch_plain_c<16>(G, a, q, s); break;
-    default: launch_plain_c<32>(G, a, q, s); break;
-  }
-}
-
-template <int C, int G>
-static const void* persistent_fn() {
-  return reinterpret_cast<const void*>(&k_flow_persistent<C, G>);
+  with_class(cls, [&](auto cc, auto ww) {
+    with_lanes(G, [&](auto gg) {
+      constexpr int C = decltype(cc)::value, W = decltype(ww)::value, GG = decltype(gg)::value;
+      k_flow_plain<C, W, GG><<<(unsigned)a.n_cols, 64 * W, 0, s>>>(a, q);
+    });
+  });
 }
 
 static const void* persistent_kernel(int cls, int G) {
-#define FT_PK(CC)                                   \
-  switch (G) {                                      \
-    case 1: return persistent_fn<CC, 1>();          \
-    case 2: return persistent_fn<CC, 2>();          \
-    case 4: return persistent_fn<CC, 4>();          \
-    case 8: return persistent_fn<CC, 8>();          \
-    default: return persistent_fn<CC, 16>();        \
-  }
-  switch (cls) {
-    case 0: FT_PK(2)
-    case 1: FT_PK(4)
-    case 2: FT_PK(8)
-    case 3: FT_PK(16)
-    default: FT_PK(32)
-  }
-#undef FT_PK
-}
-
-template <int C>
-static void launch_persistent_c(int G, unsigned blocks, const PairArgs& a, const int64_t* list, const int64_t* offsets,
-                                int64_t n_q, int cls, uint32_t* counters, int chunk, hipStream_t s) {
-  switch (G) {
-    case 1: k_flow_persistent<C, 1><<<blocks, 64, 0, s>>>(a, list, offsets, n_q, cls, counters, chunk); break;
-    case 2: k_flow_persistent<C, 2><<<blocks, 64, 0, s>>>(a, list, offsets, n_q, cls, counters, chunk); break;
-    case 4: k_flow_persistent<C, 4><<<blocks, 64, 0, s>>>(a, list, offsets, n_q, cls, counters, chunk); break;
-    case 8: k_flow_persistent<C, 8><<<blocks, 64, 0, s>>>(a, list, offsets, n_q, cls, counters, chunk); break;
-    default: k_flow_persistent<C, 16><<<blocks, 64, 0, s>>>(a, list, offsets, n_q, cls, counters, chunk); break;
-  }
+  const void* fn = nullptr;
+  with_class(cls, [&](auto cc, auto ww) {
+    with_lanes(G, [&](auto gg) {
+      constexpr int C = decltype(cc)::value, W = decltype(ww)::value, GG = decltype(gg)::value;
+      fn = reinterpret_cast<const void*>(&k_flow_persistent<C, W, GG>);
+    });
+  });
+  return fn;
 }
 
 static void launch_persistent(int cls, int G, unsigned blocks, const PairArgs& a, const int64_t* list,
                               const int64_t* offsets, int64_t n_q, uint32_t* counters, int chunk, hipStream_t s) {
-  switch (cls) {
-    case 0: launch_persistent_c<2>(G, blocks, a, list, offsets, n_q, cls, counters, chunk, s); break;
-    case 1: launch_persistent_c<4>(G, blocks, a, list, offsets, n_q, cls, counters, chunk, s); break;
-    case 2: launch_persistent_c<8>(G, blocks, a, list, offsets, n_q, cls, counters, chunk, s); break;
-    case 3: launch_persistent_c<16>(G, blocks, a, list, offsets, n_q, cls, counters, chunk, s); break;
-    default: launch_persistent_c<32>(G, blocks, a, list, offsets, n_q, cls, counters, chunk, s); break;
-  }
+  with_class(cls, [&](auto cc, auto ww) {
+    with_lanes(G, [&](auto gg) {
+      constexpr int C = decltype(cc)::value, W = decltype(ww)::value, GG = decltype(gg)::value;
+      k_flow_persistent<C, W, GG><<<blocks, 64 * W, 0, s>>>(a, list, offsets, n_q, cls, counters, chunk);
+    });
+  });
 }
 
 // ------------------------------------------------------------- batched --
@@ -226,7 +213,7 @@ static void enqueue_persistent(const PairArgs& a, const BatchedPlan& P, hipStrea
 
 static unsigned occupancy_blocks(ft_index* ix, int cls, int G) {
   int per_cu = 0;
-  FT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel(cls, G), 64, 0));
+  FT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel(cls, G), 64 * CLASS_W[cls], 0));
   per_cu = std::max(1, per_cu);
   return (unsigned)(per_cu * ix->n_cu);
 }

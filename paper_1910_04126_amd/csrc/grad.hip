@@ -49,22 +49,22 @@ struct SaveArgs {
 
 template <int C, int G, int VEC>
 __global__ __launch_bounds__(64) void k_flow_save(SaveArgs a) {
-  __shared__ FlowLds<C> L;
+  __shared__ FlowLds<C, 1> L;
   const int64_t p = blockIdx.x;
   const int64_t q = a.pair_q[p], doc = a.pair_d[p];
   const int64_t qa = a.q_off[q], da = a.d_off[doc];
   const int nq = (int)(a.q_off[q + 1] - qa), nd = (int)(a.d_off[doc + 1] - da);
-  if (nq + nd > FlowLds<C>::N) {
+  if (nq + nd > FlowLds<C, 1>::N) {
     if (threadIdx.x == 0) atomicOr(a.status, ERR_FLOW);
     return;
   }
   flow_stage(L, a.q_rank + qa, a.q_mass + qa, nq, a.d_rank + da, a.d_mass + da, nd);
   FlowSave sv = a.sv;
   sv.base = a.base[p];
-  const int E = flow_match<C, true>(L, nq, nd, a.st, a.V, a.B, sv, a.status);
+  const int E = flow_match<C, 1, true>(L, nq, nd, a.st, a.V, a.B, sv, a.status);
   if (threadIdx.x == 0) a.count[p] = E;
   if (a.cost) {
-    const double c = flow_price<C, G, VEC>(L, E, a.X, a.perm, a.d, a.d);
+    const double c = flow_price<C, 1, G, VEC>(L, E, a.X, a.perm, a.d, a.d);
     if (threadIdx.x == 0) a.cost[p] = (float)ldexp(c, -a.Q);
   }
 }
