@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "common.h"
@@ -121,21 +122,32 @@ __global__ __launch_bounds__(QT_THREADS) void k_qt_tile(
 // numbered densely (all depth-1 nodes, then depth 2, ...), so a slice's list
 // directory is a plain array of end offsets indexed by cell number.
 //
-// A workgroup takes one (query, slice): it looks up the query's cells in the
-// slice directory, cuts the non-empty lists into pieces of QP_PIECE entries,
-// and its wavefronts add 2^(B - depth) * min(query mass, doc mass) into one
-// u64 LDS counter per doc; the keys S_q + S_d - 2 * counter follow.
+// A workgroup takes one (query, slice): it looks up up to QP_ENTRIES of the
+// query's cells at a time in the slice directory, cuts the non-empty lists
+// into pieces of QP_PIECE entries (a table in LDS maps each piece to its
+// list), and its wavefronts, two pieces at a time, add
+// side(depth) * min(query mass, doc mass) into one LDS counter per doc; the
+// keys S_q + S_d - 2 * counter follow.  Counters are u32 in units of the
+// deepest side when every sum fits (Q + height <= 32: a depth's cells
+// partition the mass, so the sum is below 2^(Q + height)), else u64 in grid
+// units; either way they fill 32 KB, so a slice is 8192 or 4096 docs.
 
 constexpr int QP_THREADS = 512;
 constexpr int QP_WAVES = QP_THREADS / 64;
-constexpr int QP_SLICE_MAX = 4096;  // docs per slice (u64 LDS counters)
-constexpr int QP_PIECE = 256;       // list entries per wavefront task
+constexpr int QP_ACC_BYTES = 32 * 1024;
+constexpr int QP_ENTRIES = 256;  // query cells per round (an item index fits a byte)
+constexpr int QP_PIECE = 256;    // list entries per piece
+constexpr int QP_U = 2;          // pieces in flight per wavefront
+// a list in a slice has at most one entry per doc
+constexpr int QP_MAX_PIECES = QP_ENTRIES * (QP_ACC_BYTES / 4) / QP_PIECE;
+
+inline bool post_narrow(int Q, int height) { return Q + height <= 32; }
 
 // Slice size for n docs: at least 8 slices when the docs allow, at most
-// QP_SLICE_MAX docs each.
-inline int64_t post_slice_size(int64_t n) {
+// smax docs each.
+inline int64_t post_slice_size(int64_t n, int64_t smax) {
   int64_t S = 64;
-  while (S * 2 <= QP_SLICE_MAX && S * 2 * 8 <= n) S *= 2;
+  while (S * 2 <= smax && S * 2 * 8 <= n) S *= 2;
   return S;
 }
 
@@ -210,16 +222,21 @@ __global__ __launch_bounds__(64) void k_post_fill(const int64_t* __restrict__ eo
 // Workgroup per (query, slice).  Workgroups are dealt to the 8 XCDs in turn,
 // so block b runs on XCD b % 8; slices are given out so that each XCD walks
 // one slice at a time through all the queries of the launch, keeping that
-// slice's lists in its L2.
+// slice's lists in its L2.  H: the tree height (narrow counters).
+template <bool NARROW>
 __global__ __launch_bounds__(QP_THREADS) void k_qt_post(
     const uint2* __restrict__ post, const uint32_t* __restrict__ dir, const uint32_t* __restrict__ cbase,
     int64_t n_cells, int64_t S, int64_t n_sl, const int64_t* __restrict__ d_eoff, const uint64_t* __restrict__ d_S,
     int64_t n_docs, const int64_t* __restrict__ q_eoff, const uint32_t* __restrict__ q_ekey,
-    const uint32_t* __restrict__ q_emass, const uint64_t* __restrict__ q_S, int64_t r0, int64_t n_rows, int B,
-    uint64_t* __restrict__ keys) {
-  __shared__ unsigned long long acc[QP_SLICE_MAX];
-  __shared__ uint4 items[QP_THREADS];
-  __shared__ uint32_t pstart[QP_THREADS];
+    const uint32_t* __restrict__ q_emass, const uint64_t* __restrict__ q_S, int64_t r0, int64_t n_rows, int B, int H,
+    uint64_t* __restrict__ keys, unsigned long long* __restrict__ minmax) {
+  using Acc = typename std::conditional<NARROW, uint32_t, unsigned long long>::type;
+  constexpr int SMAX = QP_ACC_BYTES / sizeof(Acc);
+  __shared__ Acc acc[SMAX];
+  __shared__ uint4 items[QP_ENTRIES];          // list start, length, query mass, shift
+  __shared__ uint32_t pstart[QP_ENTRIES];      // first piece of each list
+  __shared__ uint8_t pitem[QP_MAX_PIECES];     // list of each piece
+  __shared__ unsigned long long red[2][QP_WAVES];
   __shared__ unsigned long long ctr;
   const int64_t blk = blockIdx.x;
   const int64_t local = blk >> 3;
@@ -229,15 +246,16 @@ __global__ __launch_bounds__(QP_THREADS) void k_qt_post(
   const int tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
   const int64_t q = r0 + row, d0 = sl * S;
   const int nd = (int)(n_docs - d0 < S ? n_docs - d0 : S);
-  for (int i = tid; i < nd; i += QP_THREADS) acc[i] = 0ull;
+  for (int i = tid; i < nd; i += QP_THREADS) acc[i] = 0;
   const uint32_t* D = dir + sl * n_cells;
   const uint2* P = post + d_eoff[d0];
   const int64_t e0 = q_eoff[q];
   const int ne = (int)(q_eoff[q + 1] - e0);
-  for (int c0 = 0; c0 < ne; c0 += QP_THREADS) {
+  const int top = NARROW ? H : B;
+  for (int c0 = 0; c0 < ne; c0 += QP_ENTRIES) {
     if (tid == 0) ctr = 0ull;
     __syncthreads();
-    if (c0 + tid < ne) {
+    if (tid < QP_ENTRIES && c0 + tid < ne) {
       const uint32_t key = q_ekey[e0 + c0 + tid];
       const uint32_t c = cell_number(cbase, key);
       const uint32_t o1 = D[c], o0 = c ? D[c - 1] : 0u;
@@ -245,40 +263,89 @@ __global__ __launch_bounds__(QP_THREADS) void k_qt_post(
         const uint32_t len = o1 - o0, np = (len + QP_PIECE - 1) / QP_PIECE;
         const unsigned long long old = atomicAdd(&ctr, (1ull << 32) | np);
         const uint32_t idx = (uint32_t)(old >> 32);
-        items[idx] = make_uint4(o0, len, q_emass[e0 + c0 + tid], (uint32_t)B - (key >> KEY_DEPTH_SHIFT));
-        pstart[idx] = (uint32_t)old;  // pieces before this list: increasing with idx
+        items[idx] = make_uint4(o0, len, q_emass[e0 + c0 + tid], (uint32_t)top - (key >> KEY_DEPTH_SHIFT));
+        pstart[idx] = (uint32_t)old;
       }
     }
     __syncthreads();
     const unsigned long long cc = ctr;
     const uint32_t n_items = (uint32_t)(cc >> 32), n_pieces = (uint32_t)cc;
-    for (uint32_t p = w; p < n_pieces; p += QP_WAVES) {
-      uint32_t lo = 0, hi = n_items - 1;  // last list whose first piece is <= p
-      while (lo < hi) {
-        const uint32_t mid = (lo + hi + 1) >> 1;
-        if (pstart[mid] <= p) lo = mid;
-        else hi = mid - 1;
-      }
-      const uint4 it = items[lo];
-      const uint32_t off = (p - pstart[lo]) * QP_PIECE;
-      const uint32_t n = min((uint32_t)QP_PIECE, it.y - off);
-      const uint2* src = P + it.x + off;
+    for (uint32_t i = tid; i < n_items; i += QP_THREADS) {
+      const uint32_t p0 = pstart[i], np = (items[i].y + QP_PIECE - 1) / QP_PIECE;
+      for (uint32_t j = 0; j < np; ++j) pitem[p0 + j] = (uint8_t)i;
+    }
+    __syncthreads();
+    for (uint32_t p0 = w * QP_U; p0 < n_pieces; p0 += QP_WAVES * QP_U) {
+      uint2 e[QP_U][QP_PIECE / 64];
+      uint32_t am[QP_U], sh[QP_U], cnt[QP_U];
 #pragma unroll
-      for (int u = 0; u < QP_PIECE / 64; ++u) {
-        const uint32_t j = u * 64 + lane;
-        if (j < n) {
-          const uint2 e = src[j];
-          atomicAdd(&acc[e.x], (unsigned long long)min(it.z, e.y) << it.w);
+      for (int u = 0; u < QP_U; ++u) {
+        const uint32_t p = p0 + u;
+        cnt[u] = 0;
+        am[u] = sh[u] = 0;
+        const uint2* src = P;
+        if (p < n_pieces) {
+          const uint32_t it = pitem[p];
+          const uint4 item = items[it];
+          const uint32_t off = (p - pstart[it]) * QP_PIECE;
+          cnt[u] = min((uint32_t)QP_PIECE, item.y - off);
+          am[u] = item.z;
+          sh[u] = item.w;
+          src = P + item.x + off;
+        }
+#pragma unroll
+        for (int j = 0; j < QP_PIECE / 64; ++j) {
+          const uint32_t x = j * 64 + lane;
+          e[u][j] = x < cnt[u] ? src[x] : make_uint2(0u, 0u);
         }
       }
+#pragma unroll
+      for (int u = 0; u < QP_U; ++u)
+#pragma unroll
+        for (int j = 0; j < QP_PIECE / 64; ++j)
+          if ((uint32_t)(j * 64 + lane) < cnt[u]) atomicAdd(&acc[e[u][j].x], (Acc)min(am[u], e[u][j].y) << sh[u]);
     }
     __syncthreads();
   }
-  __syncthreads();
   const uint64_t Sq = q_S[q];
   uint64_t* out = keys + row * n_docs + d0;
   const uint64_t* Sd = d_S + d0;
-  for (int i = tid; i < nd; i += QP_THREADS) out[i] = Sq + Sd[i] - 2ull * acc[i];
+  const int up = NARROW ? B - H : 0;
+  unsigned long long mn = ~0ull, mx = 0ull;
+  for (int i = tid; i < nd; i += QP_THREADS) {
+    const uint64_t key = Sq + Sd[i] - (((uint64_t)acc[i] << up) << 1);
+    out[i] = key;
+    mn = key < mn ? key : mn;
+    mx = key > mx ? key : mx;
+  }
+  // the row's smallest and largest key, for the selection that follows
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long a = __shfl_xor(mn, o, 64), b = __shfl_xor(mx, o, 64);
+    mn = a < mn ? a : mn;
+    mx = b > mx ? b : mx;
+  }
+  if (lane == 0) {
+    red[0][w] = mn;
+    red[1][w] = mx;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int j = 1; j < QP_WAVES; ++j) {
+      mn = red[0][j] < mn ? red[0][j] : mn;
+      mx = red[1][j] > mx ? red[1][j] : mx;
+    }
+    atomicMin(&minmax[2 * row], mn);
+    atomicMax(&minmax[2 * row + 1], mx);
+  }
+}
+
+__global__ void k_minmax_init(unsigned long long* __restrict__ minmax, int64_t rows) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < rows) {
+    minmax[2 * i] = ~0ull;
+    minmax[2 * i + 1] = 0ull;
+  }
 }
 
 // Explicit (query, doc) pairs: one wavefront per pair, the query table in LDS.
@@ -331,7 +398,8 @@ constexpr int SLOTS_SMALL = 4096, SLOTS_LARGE = 8192;
 static void prepare_postings(ft_index* ix, hipStream_t s) {
   if (ix->post_nsl > 0) return;
   const int64_t n = ix->docs.n;
-  const int64_t S = post_slice_size(n), n_sl = ceil_div(n, S);
+  const bool narrow = post_narrow(ix->Q, ix->height);
+  const int64_t S = post_slice_size(n, narrow ? QP_ACC_BYTES / 4 : QP_ACC_BYTES / 8), n_sl = ceil_div(n, S);
   const int64_t n_cells = std::max<int64_t>(1, ix->n_nodes - 1);
   FT_REQUIRE(n_sl * n_cells <= (int64_t(1) << 32), FT_ERANGE,
              "the inverted Quadtree lists would need more than 16 GiB of directory");
@@ -384,15 +452,22 @@ extern "C" ft_status ft_quadtree_knn(ft_index* ix, const int64_t* q_off, const u
     if (!cand) prepare_postings(ix, s);
     for (int64_t r0 = 0; r0 < n_q; r0 += rows_per_chunk) {
       const int64_t r1 = std::min(n_q, r0 + rows_per_chunk);
+      unsigned long long* minmax = nullptr;  // per-row key range, when the ranking kernel gives it
       if (!cand) {
         // all docs: the inverted lists, one workgroup per (query, slice)
         const int64_t rows = r1 - r0, groups = ceil_div(ix->post_nsl, 8);
         FT_REQUIRE(groups * 8 * rows < (int64_t(1) << 31), FT_ERANGE, "too many (query, slice) workgroups");
-        k_qt_post<<<(unsigned)(groups * 8 * rows), QP_THREADS, 0, s>>>(
-            ix->post.as<uint2>(), ix->post_dir.as<uint32_t>(), ix->post_cbase.as<uint32_t>(), ix->post_cells,
-            ix->post_slice, ix->post_nsl, ix->docs.ecnt.as<int64_t>(), ix->docs.S.as<uint64_t>(), n_cols,
-            ix->qry.ecnt.as<int64_t>(), ix->qry.ekey.as<uint32_t>(), ix->qry.emass.as<uint32_t>(),
-            ix->qry.S.as<uint64_t>(), r0, rows, ix->B, keys);
+        minmax = (unsigned long long*)ix->ws_sel.ensure(rows_per_chunk * 16);
+        k_minmax_init<<<(unsigned)ceil_div(rows, 256), 256, 0, s>>>(minmax, rows);
+        auto go = [&](auto narrow) {
+          k_qt_post<decltype(narrow)::value><<<(unsigned)(groups * 8 * rows), QP_THREADS, 0, s>>>(
+              ix->post.as<uint2>(), ix->post_dir.as<uint32_t>(), ix->post_cbase.as<uint32_t>(), ix->post_cells,
+              ix->post_slice, ix->post_nsl, ix->docs.ecnt.as<int64_t>(), ix->docs.S.as<uint64_t>(), n_cols,
+              ix->qry.ecnt.as<int64_t>(), ix->qry.ekey.as<uint32_t>(), ix->qry.emass.as<uint32_t>(),
+              ix->qry.S.as<uint64_t>(), r0, rows, ix->B, ix->height, keys, minmax);
+        };
+        if (post_narrow(ix->Q, ix->height)) go(std::true_type{});
+        else go(std::false_type{});
         FT_HIP(hipGetLastError());
       } else {
         // candidate lists: one query per workgroup, its table in LDS
@@ -422,7 +497,7 @@ extern "C" ft_status ft_quadtree_knn(ft_index* ix, const int64_t* q_off, const u
         FT_HIP(hipStreamSynchronize(s));  // the tile table is reused by the next chunk
       }
       topk_rows(keys, r1 - r0, n_cols, cand ? cand + r0 * n_cols : nullptr, k, out_key + r0 * k, out_doc + r0 * k,
-                s);
+                s, reinterpret_cast<const uint64_t*>(minmax));
     }
   });
 }

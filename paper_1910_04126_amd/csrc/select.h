@@ -9,9 +9,10 @@ namespace ft {
 
 // For each of `rows` rows of n keys (row-major), write the k smallest
 // (key, doc) pairs ascending; doc = docs[row * n + c] when docs is given, else
-// the column c.  Launches only.
+// the column c.  minmax, when given, holds each row's smallest and largest
+// key ([rows][2]).  Launches only.
 void topk_rows(const uint64_t* keys, int64_t rows, int64_t n, const int64_t* docs, int k, uint64_t* out_key,
-               int64_t* out_doc, hipStream_t s);
+               int64_t* out_doc, hipStream_t s, const uint64_t* minmax = nullptr);
 void topk_rows(const float* keys, int64_t rows, int64_t n, const int64_t* docs, int k, float* out_key,
                int64_t* out_doc, hipStream_t s);
 

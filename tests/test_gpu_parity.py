@@ -155,6 +155,22 @@ def test_quadtree_knn_tiny_all_and_cand(ft):
                    exact=True)
 
 
+@pytest.mark.parametrize("Q", [30, 31])
+def test_quadtree_knn_wide_counters(ft, Q):
+    """Q + tree height > 32: the ranking of all docs keeps 64-bit per-doc
+    counters (and 4096-doc slices) instead of the scaled 32-bit ones."""
+    say("quadtree knn: tiny with Q=%d (64-bit counters)" % Q)
+    ds = gen.make("tiny", Q=Q, n_docs=1500, n_queries=6)
+    ix = build_index(ft, ds)
+    assert ix.info()["Q"] + ix.info()["height"] > 32
+    T = oracle_tree(ds)
+    docs = np.arange(ds.n_docs)
+    M = oracle_matrix(T, ds, range(ds.n_queries), docs, "qt")
+    keys, kd = ft.quadtree_knn(ix, *queries(ds), 40)
+    for q in range(ds.n_queries):
+        check_topk(kd[q].cpu().numpy(), keys[q].cpu().numpy().view(np.uint64), M[q], docs, 40, exact=True)
+
+
 # --------------------------------------------------------------- flowtree --
 
 def check_flows(ft, ds, ix, T, pairs, q_sel=None):
@@ -418,6 +434,39 @@ def test_long_rows_tie_bucket_sizes(ft, reps):
         k = int(min(1024, max(1, (M[q] < dup_key).sum() + 1)))
         keys, kd = ft.quadtree_knn(ix, *queries(ds), k)
         check_topk(kd[q].cpu().numpy(), keys[q].cpu().numpy().view(np.uint64), M[q], docs, k, exact=True)
+
+
+def test_long_rows_refined_bucket(ft):
+    """Thousands of distinct keys packed next to the query: the first digit
+    histogram puts them all in one bucket larger than the LDS tie buffer, and
+    the select must refine into the next digits instead of giving up."""
+    say("select: 3000 near-duplicates of the query among 7200 docs (digit refinement)")
+    base = gen.make("tiny", n_docs=4200, n_queries=2)
+    one = base.doc_id[base.doc_off[3]:base.doc_off[4]]
+    onem = base.doc_mass[base.doc_off[3]:base.doc_off[4]].astype(np.int64)
+    reps = 3000
+    var = np.tile(onem, (reps, 1))
+    delta = np.arange(1, reps + 1)
+    assert onem[0] > reps
+    var[:, 0] -= delta  # move delta mass units from the first point to the second
+    var[:, 1] += delta
+    sizes = np.concatenate([np.diff(base.doc_off), np.full(reps, len(one))])
+    off = np.zeros(len(sizes) + 1, np.int64)
+    off[1:] = np.cumsum(sizes)
+    ids = np.concatenate([base.doc_id, np.tile(one, reps)])
+    m = np.concatenate([base.doc_mass, var.reshape(-1).astype(np.uint32)])
+    q_off = np.array([0, len(one), len(one) + base.q_off[1]], np.int64)
+    q_id = np.concatenate([one, base.q_id[:base.q_off[1]]])
+    q_m = np.concatenate([onem.astype(np.uint32), base.q_mass[:base.q_off[1]]])
+    ds = gen.Dataset("near", base.X, base.shift, base.B, base.Q, off, ids, m, q_off, q_id, q_m, 5)
+    ix = build_index(ft, ds)
+    T = oracle_tree(ds)
+    docs = np.arange(ds.n_docs)
+    M = oracle_matrix(T, ds, range(2), docs, "qt")
+    for k in (1000, 1024):
+        keys, kd = ft.quadtree_knn(ix, *queries(ds), k)
+        for q in range(2):
+            check_topk(kd[q].cpu().numpy(), keys[q].cpu().numpy().view(np.uint64), M[q], docs, k, exact=True)
 
 
 def test_long_rows_many_ties(ft):
