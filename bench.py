@@ -31,6 +31,28 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 
+# HBM bytes of one launch of the persistent Flowtree graph on the batched
+# workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a 1 GiB copy
+# (profiles/flowtree_batched_uneven_hbm_traffic.md), valid while the kernel
+# sources hash to TRAFFIC_SOURCES_SHA1.
+TRAFFIC_BYTES = 2.557e11
+TRAFFIC_SOURCES = ("paper_1910_04126_amd/csrc/flow.h", "paper_1910_04126_amd/csrc/flowtree.hip",
+                   "paper_1910_04126_amd/csrc/wave.h", "paper_1910_04126_amd/csrc/common.h")
+TRAFFIC_SOURCES_SHA1 = "cd24ae2e8e666c9a68bff30630285a2479c7844c"
+
+
+def measured_traffic(workload):
+    """The counted bytes when they were taken on this workload and these
+    kernel sources, else None."""
+    import hashlib
+    if workload != "batched":
+        return None
+    h = hashlib.sha1()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return TRAFFIC_BYTES if h.hexdigest() == TRAFFIC_SOURCES_SHA1 else None
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -182,7 +204,7 @@ def main():
         "config": {"workload": desc, "queries": n_q, "docs": ds.n_docs, "V": ds.V, "d": ds.d,
                    "prune_k": prune, "k": k, "flowtree_pairs_per_step": ft_pairs},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.workload),
                      "kernel": "k_flow_persistent (all size classes, one graph)",
                      "kernel_ms": round(kms, 3), "algorithmic_bytes": alg_bytes},
         "stages": {"quadtree_prune_ms": round(float(np.mean(stage_qt)), 3),
