@@ -224,6 +224,30 @@ def test_flows_shared_points(ft):
     assert (costs[:, 0].cpu().numpy() == 0).all()
 
 
+def test_flows_class_edges_and_max_support(ft):
+    """Pairs of 2 to 2048 merged items: both sides of every size-class edge
+    (128/129, 256/257, 512/513, 1024/1025), the largest supports (1024 +
+    1024) and single-point distributions.  Flows bit-exact, costs to the
+    oracle, plain == batched."""
+    say("flows: size-class edges, single points, 1024 + 1024 items")
+    base = gen.make("tiny", n_docs=2, n_queries=1)
+    rng = np.random.default_rng(11)
+
+    def csr(sizes):
+        off = np.zeros(len(sizes) + 1, np.int64)
+        off[1:] = np.cumsum(sizes)
+        ids = np.concatenate([rng.choice(base.V, s, replace=False) for s in sizes]).astype(np.uint32)
+        return off, ids, gen.uniform_masses(off, ids, base.Q)
+
+    do, di, dm = csr([1, 63, 64, 65, 192, 193, 448, 449, 960, 961, 1024])
+    qo, qi, qm = csr([1, 64, 1024])
+    ds = gen.Dataset("edges", base.X, base.shift, base.B, base.Q, do, di, dm, qo, qi, qm, 5)
+    ix = build_index(ft, ds)
+    T = oracle_tree(ds)
+    check_flows(ft, ds, ix, T, [(q, d) for q in range(3) for d in range(ds.n_docs)])
+    flow_knn_check(ft, ds, ix, T, ds.n_docs)
+
+
 def flow_knn_check(ft, ds, ix, T, k, cand=None, modes=("plain", "batched"), q_sel=None):
     n_q = ds.n_queries
     res = {}
