@@ -199,23 +199,29 @@ __global__ __launch_bounds__(1024) void k_post_scan(uint32_t* __restrict__ dir, 
   }
 }
 
-// Wavefront per doc: place the doc's (doc in slice, mass) entries.  The
+// Wavefront per slice: place the slice's (doc in slice, mass) entries doc by
+// doc, so every cell's list comes out in doc order (consecutive lanes of the
+// ranking kernel then add into nearby, mostly distinct LDS banks).  A doc
+// touches each cell once, so its lanes never share a counter; the barrier
+// after each doc orders its counter updates before the next doc's.  The
 // directory counters run from each list's start to its end, which is what
-// the query kernel reads.  Entry order inside a list is immaterial (integer
-// sums).
+// the ranking kernel reads.
 __global__ __launch_bounds__(64) void k_post_fill(const int64_t* __restrict__ eoff, const uint32_t* __restrict__ ekey,
                                                   const uint32_t* __restrict__ emass, int64_t n_docs, int64_t S,
                                                   int64_t n_cells, const uint32_t* __restrict__ cbase,
                                                   uint32_t* __restrict__ dir, uint2* __restrict__ post) {
-  for (int64_t d = blockIdx.x; d < n_docs; d += gridDim.x) {
-    const int64_t sl = d / S;
-    uint32_t* D = dir + sl * n_cells;
-    uint2* P = post + eoff[sl * S];
-    const uint32_t local = (uint32_t)(d - sl * S);
+  const int64_t sl = blockIdx.x;
+  const int64_t d0 = sl * S, d1 = d0 + S < n_docs ? d0 + S : n_docs;
+  uint32_t* D = dir + sl * n_cells;
+  uint2* P = post + eoff[d0];
+  for (int64_t d = d0; d < d1; ++d) {
+    const uint32_t local = (uint32_t)(d - d0);
     for (int64_t e = eoff[d] + lane_id(); e < eoff[d + 1]; e += 64) {
       const uint32_t pos = atomicAdd(&D[cell_number(cbase, ekey[e])], 1u);
       P[pos] = make_uint2(local, emass[e]);
     }
+    __threadfence();
+    __syncthreads();
   }
 }
 
@@ -413,8 +419,8 @@ static void prepare_postings(ft_index* ix, hipStream_t s) {
   const unsigned g = (unsigned)std::min<int64_t>(n, 1 << 20);
   k_post_count<<<g, 64, 0, s>>>(ix->docs.ecnt.as<int64_t>(), ix->docs.ekey.as<uint32_t>(), n, S, n_cells, cbase, dir);
   k_post_scan<<<(unsigned)n_sl, 1024, 0, s>>>(dir, n_cells);
-  k_post_fill<<<g, 64, 0, s>>>(ix->docs.ecnt.as<int64_t>(), ix->docs.ekey.as<uint32_t>(),
-                               ix->docs.emass.as<uint32_t>(), n, S, n_cells, cbase, dir, post);
+  k_post_fill<<<(unsigned)n_sl, 64, 0, s>>>(ix->docs.ecnt.as<int64_t>(), ix->docs.ekey.as<uint32_t>(),
+                                            ix->docs.emass.as<uint32_t>(), n, S, n_cells, cbase, dir, post);
   FT_HIP(hipGetLastError());
   FT_HIP(hipStreamSynchronize(s));
   ix->post_slice = S;
