@@ -113,17 +113,40 @@ __device__ int flow_match(FlowLds<C, W>& L, const int nq, const int nd, const ui
     }
   }
   __syncthreads();
-  // ---- adjacent LCA depths and the depths present
+  // ---- adjacent LCA depths and the depths present: all range-minimum reads
+  // of a lane are issued before any is used
   uint32_t mask = 1u;
-  for (int c = 0; c < C; ++c) {
-    const int t = t0 + c;
-    if (t < n) {
-      int l = -1;
-      if (t + 1 < n) {
-        l = lca_depth(st, V, B, L.rank[t], L.rank[t + 1]);
-        mask |= 1u << l;
+  {
+    int64_t ia[C], ib[C];
+    uint8_t va[C], vb[C];
+    bool same[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int t = t0 + c;
+      const bool valid = t + 1 < n;
+      const uint32_t ra = valid ? L.rank[t] : 0u, rb = valid ? L.rank[t + 1] : 0u;
+      const uint32_t len = rb - ra;  // Morton order: ra <= rb
+      same[c] = len == 0u;
+      const int j = same[c] ? 0 : 31 - __clz(len);
+      ia[c] = (int64_t)j * V + ra;
+      ib[c] = (int64_t)j * V + (rb - (same[c] ? 0u : (1u << j)));
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      va[c] = st[ia[c]];
+      vb[c] = st[ib[c]];
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int t = t0 + c;
+      if (t < n) {
+        int l = -1;
+        if (t + 1 < n) {
+          l = same[c] ? B : (va[c] < vb[c] ? va[c] : vb[c]);
+          mask |= 1u << l;
+        }
+        L.lcn[t] = (int8_t)l;
       }
-      L.lcn[t] = (int8_t)l;
     }
   }
   mask = wave_or(mask);
@@ -312,6 +335,24 @@ __device__ int flow_match(FlowLds<C, W>& L, const int nq, const int nd, const ui
   return E;
 }
 
+// Sum over aligned groups of G lanes (G <= 16, inside one DPP row of 16),
+// left in every lane of the group: neighbours, then pairs of neighbours by
+// quad permutes, then halves and whole rows by mirrors.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+
+template <int G>
+__device__ __forceinline__ float group_sum(float v) {
+  static_assert(G >= 1 && G <= 16 && (G & (G - 1)) == 0, "G must be a power of two <= 16");
+  if (G >= 2) v += dpp_f32<0xB1>(v);   // quad_perm [1,0,3,2]
+  if (G >= 4) v += dpp_f32<0x4E>(v);   // quad_perm [2,3,0,1]
+  if (G >= 8) v += dpp_f32<0x141>(v);  // row_half_mirror
+  if (G >= 16) v += dpp_f32<0x140>(v); // row_mirror
+  return v;
+}
+
 // Euclidean price of the matches: sum eta * ||x_doc - x_query||_2 (float32
 // distances, float64 accumulation).  G lanes share one match, and a lane
 // reads up to PV float4 (or floats when VEC == 1) of each row per pass, all
@@ -370,8 +411,7 @@ __device__ double flow_price(FlowLds<C, W>& L, const int E, const float* __restr
         }
       }
     }
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    acc = group_sum<G>(acc);
     if (sub == 0 && e < E) prod[e] = live ? (double)eta * (double)sqrtf(acc) : 0.0;
   }
   __syncthreads();

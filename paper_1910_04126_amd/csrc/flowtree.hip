@@ -56,6 +56,12 @@ __device__ __forceinline__ void flow_one(FlowLds<C, W>& L, const PairArgs& a, co
   __syncthreads();
 }
 
+// Persistent workgroups of several wavefronts with 4 items per lane are
+// latency-bound on their row reads and fit in 128 VGPRs without spilling:
+// they are held there, four wavefronts per SIMD.
+template <int C, int W>
+constexpr int flow_min_waves() { return (W >= 2 && C <= 4) ? 4 : 1; }
+
 // Plain: workgroup b handles column b of query q.
 template <int C, int W, int G>
 __global__ __launch_bounds__(64 * W) void k_flow_plain(PairArgs a, int64_t q) {
@@ -66,7 +72,7 @@ __global__ __launch_bounds__(64 * W) void k_flow_plain(PairArgs a, int64_t q) {
 // Persistent: workgroups grab chunks of the class's pair list until it is
 // used up.
 template <int C, int W, int G>
-__global__ __launch_bounds__(64 * W) void k_flow_persistent(PairArgs a, const int64_t* __restrict__ list,
+__global__ __launch_bounds__(64 * W, (flow_min_waves<C, W>())) void k_flow_persistent(PairArgs a, const int64_t* __restrict__ list,
                                                             const int64_t* __restrict__ offsets, int64_t n_q, int cls,
                                                             uint32_t* __restrict__ counters, int chunk) {
   __shared__ FlowLds<C, W> L;
