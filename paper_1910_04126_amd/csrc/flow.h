@@ -353,13 +353,30 @@ __device__ __forceinline__ float group_sum(float v) {
   return v;
 }
 
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const uint64_t b = (uint64_t)__double_as_longlong(x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xF, 0xF, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// Sum over each row of 16 lanes, left in every lane of the row.
+__device__ __forceinline__ double row_sum_f64(double v) {
+  v += dpp_f64<0xB1>(v);
+  v += dpp_f64<0x4E>(v);
+  v += dpp_f64<0x141>(v);
+  v += dpp_f64<0x140>(v);
+  return v;
+}
+
 // Euclidean price of the matches: sum eta * ||x_doc - x_query||_2 (float32
 // distances, float64 accumulation).  G lanes share one match, and a lane
 // reads up to PV float4 (or floats when VEC == 1) of each row per pass, all
 // issued before any is used.  Each match's product lands in LDS (over the
-// prefix arrays, free by now) and wavefront 0 adds them up in one fixed
-// order, so a cost does not depend on W or on the schedule.  The result is
-// valid in wavefront 0.
+// prefix arrays, free by now) and wavefront 0 adds them up in an order fixed
+// by the number of matches alone, so a cost does not depend on W, G or the
+// schedule.  The result is valid in wavefront 0.
 template <int C, int W, int G, int VEC>
 __device__ double flow_price(FlowLds<C, W>& L, const int E, const float* __restrict__ X,
                              const uint32_t* __restrict__ row_of_rank, const int stride, const int d) {
@@ -415,14 +432,20 @@ __device__ double flow_price(FlowLds<C, W>& L, const int E, const float* __restr
     if (sub == 0 && e < E) prod[e] = live ? (double)eta * (double)sqrtf(acc) : 0.0;
   }
   __syncthreads();
+  // a fixed order that depends on E only: lane j of wavefront 0 adds the
+  // products j, j + 64, ... in turn, then the 64 lane sums are combined by a
+  // fixed tree (rows of 16 by DPP, then the four rows)
   double cost = 0.0;
   if (tid < 64) {
-    // the order of one wavefront pricing alone: group g adds matches
-    // g, g + 64/G, ... in turn, then the groups are summed by butterfly
-    constexpr int PER1 = 64 / G;
-    if (lane % G == 0)
-      for (int e = lane / G; e < E; e += PER1) cost += prod[e];
-    cost = wave_sum(cost);
+    for (int e0 = lane; e0 < E; e0 += 4 * 64) {
+      double v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = e0 + 64 * u < E ? prod[e0 + 64 * u] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) cost += v[u];
+    }
+    cost = row_sum_f64(cost);
+    cost = (__shfl(cost, 0, 64) + __shfl(cost, 16, 64)) + (__shfl(cost, 32, 64) + __shfl(cost, 48, 64));
   }
   return cost;
 }
