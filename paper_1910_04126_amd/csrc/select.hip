@@ -74,25 +74,89 @@ constexpr int TIE_CAP = 2048;  // a power of two: the bitonic sort pads to one
 
 __device__ __forceinline__ uint64_t shr64(uint64_t x, int s) { return s >= 64 ? 0ull : x >> s; }
 
-// Rows longer than SMALL_MAX: find the bucket of the k-th smallest key by
-// histograms of 11-bit digits, starting below the bits all keys share (from
-// the row's min and max, given or computed here) and refining inside that
-// bucket while it holds more than TIE_CAP keys; one more pass collects the
-// keys below the bucket and the bucket itself, which are sorted in LDS.  A
-// final bucket of more than TIE_CAP keys is a run of equal keys, of which the
-// lowest columns are taken in order.
+constexpr int COLLECT_CAP = 4096;  // keys gathered by the one-pass path (a power of two)
+
+// Block-wide digit histograms over the keys of columns [0, n_cols): starting
+// with the bits >= hs fixed to sel, find the 11-bit bucket (then the next 11
+// bits inside it, ...) holding the target-th smallest key, until that bucket
+// holds at most stop keys or the last bit is reached.  On return, keys with
+// shr64(x, hs) < sel number `below`, and those equal to sel number `nties`.
+template <class K>
+__device__ void digit_levels(const K* __restrict__ rk, int64_t n_cols, uint32_t target, uint32_t stop, int& hs,
+                             uint64_t& sel, uint32_t& below, uint32_t& nties, uint32_t* hist, uint32_t* s_b,
+                             uint32_t* s_below) {
+  constexpr int W = 11;
+  int lo = hs - W;
+  below = 0;
+  while (true) {
+    const uint32_t dmask = (1u << (hs - lo)) - 1u;
+    for (int b = threadIdx.x; b < (1 << W); b += blockDim.x) hist[b] = 0;
+    __syncthreads();
+    for (int64_t c = threadIdx.x; c < n_cols; c += blockDim.x) {
+      const uint64_t x = sort_bits(rk[c]);
+      if (shr64(x, hs) == sel) atomicAdd(&hist[(uint32_t)(x >> lo) & dmask], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+      const int per = (1 << W) / 64;
+      uint32_t loc = 0;
+      for (int i = 0; i < per; ++i) loc += hist[threadIdx.x * per + i];
+      const uint32_t incl = wave_incl_sum(loc) + below, excl = incl - loc;
+      if (excl < target && target <= incl) {
+        uint32_t run = excl;
+        for (int i = 0; i < per; ++i) {
+          const uint32_t h = hist[threadIdx.x * per + i];
+          if (run + h >= target) {
+            *s_b = threadIdx.x * per + i;
+            *s_below = run;
+            break;
+          }
+          run += h;
+        }
+      }
+    }
+    __syncthreads();
+    const uint32_t b = *s_b;
+    below = *s_below;
+    nties = hist[b];
+    sel = (sel << (hs - lo)) | b;
+    hs = lo;
+    __syncthreads();  // hist and s_b are rewritten by the next level
+    if (nties <= stop || lo == 0) break;
+    lo = lo >= W ? lo - W : 0;
+  }
+}
+
+// Rows longer than SMALL_MAX.  All keys share the bits above the highest bit
+// where the row's min and max differ (given, or found in a first pass).
+//  * One-pass path: digit histograms over a contiguous prefix of the row (a
+//    sixteenth, at least 16384 columns; the whole row when short) find a
+//    threshold below which a little more than k * prefix / n of the prefix
+//    keys lie; one pass over the row gathers every key at or below it into
+//    LDS.  When that gathers between k and COLLECT_CAP keys, the k smallest
+//    are among them (every key left out is larger than every key taken), and
+//    a sort of the gathered keys finishes the row.
+//  * Otherwise (a threshold too tight or too loose, or a long run of equal
+//    keys) the exact path: digit histograms over the whole row, refined
+//    inside the bucket of the k-th key while it holds more than TIE_CAP keys;
+//    one pass collects the keys below that bucket and the bucket itself,
+//    which are sorted in LDS.  A final bucket of more than TIE_CAP keys is a
+//    run of equal keys, of which the lowest columns are taken in order.
 template <class K>
 __global__ __launch_bounds__(1024) void k_topk_window(const K* __restrict__ keys, int64_t n, int k,
                                                       const uint64_t* __restrict__ minmax,
                                                       K* __restrict__ out_key, int64_t* __restrict__ out_doc) {
   constexpr int W = 11;
   __shared__ uint32_t hist[1 << W];
-  __shared__ uint64_t sk[1024];
-  __shared__ uint32_t sd[1024];
-  __shared__ uint64_t tk[TIE_CAP];
-  __shared__ uint32_t td[TIE_CAP];
+  __shared__ uint64_t bufk[COLLECT_CAP];
+  __shared__ uint32_t bufd[COLLECT_CAP];
   __shared__ uint64_t red_min[16], red_max[16];
   __shared__ uint32_t s_b, s_below, s_nl, s_nt;
+  // the exact path's arrays live in the same buffers
+  uint64_t* sk = bufk;          // [1024] keys below the final bucket, then the answer
+  uint32_t* sd = bufd;
+  uint64_t* tk = bufk + 1024;   // [TIE_CAP] the final bucket
+  uint32_t* td = bufd + 1024;
   const int64_t row = blockIdx.x;
   const K* rk = keys + row * n;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -127,48 +191,55 @@ __global__ __launch_bounds__(1024) void k_topk_window(const K* __restrict__ keys
   }
   const uint64_t diff = mn ^ mx;
   const int D = diff ? 63 - __clzll((long long)diff) : 0;
-  // bits >= hs are the same in every key counted at this level; sel holds them
-  int hs = D >= W - 1 ? D + 1 : W;
-  int lo = hs - W;
-  uint64_t sel = shr64(mn, hs);
-  uint32_t below = 0, nties = 0;
-  while (true) {
-    const uint32_t dmask = (1u << (hs - lo)) - 1u;
-    for (int b = threadIdx.x; b < (1 << W); b += blockDim.x) hist[b] = 0;
+  const int hs0 = D >= W - 1 ? D + 1 : W;  // bits >= hs0 are the same in every key
+  int hs;
+  uint64_t sel;
+  uint32_t below, nties;
+
+  // ---- one-pass path
+  {
+    const int64_t ns = n <= 65536 ? n : (n / 16 > 16384 ? n / 16 : 16384);
+    const uint32_t target =
+        ns == n ? (uint32_t)k : (uint32_t)min((int64_t)ns, (int64_t)k * ns / n * 115 / 100 + 16);
+    hs = hs0;
+    sel = shr64(mn, hs0);
+    digit_levels(rk, ns, target, 16u, hs, sel, below, nties, hist, &s_b, &s_below);
+    if (threadIdx.x == 0) s_nl = 0;
     __syncthreads();
     for (int64_t c = threadIdx.x; c < n; c += blockDim.x) {
       const uint64_t x = sort_bits(rk[c]);
-      if (shr64(x, hs) == sel) atomicAdd(&hist[(uint32_t)(x >> lo) & dmask], 1u);
-    }
-    __syncthreads();
-    if (threadIdx.x < 64) {
-      const int per = (1 << W) / 64;
-      uint32_t loc = 0;
-      for (int i = 0; i < per; ++i) loc += hist[threadIdx.x * per + i];
-      const uint32_t incl = wave_incl_sum(loc) + below, excl = incl - loc;
-      if (excl < (uint32_t)k && (uint32_t)k <= incl) {
-        uint32_t run = excl;
-        for (int i = 0; i < per; ++i) {
-          const uint32_t h = hist[threadIdx.x * per + i];
-          if (run + h >= (uint32_t)k) {
-            s_b = threadIdx.x * per + i;
-            s_below = run;
-            break;
-          }
-          run += h;
+      if (shr64(x, hs) <= sel) {
+        const uint32_t p = atomicAdd(&s_nl, 1u);
+        if (p < (uint32_t)COLLECT_CAP) {
+          bufk[p] = x;
+          bufd[p] = (uint32_t)c;
         }
       }
     }
     __syncthreads();
-    const uint32_t b = s_b;
-    below = s_below;
-    nties = hist[b];
-    sel = (sel << (hs - lo)) | b;
-    hs = lo;
-    __syncthreads();  // hist and s_b are rewritten by the next level
-    if (nties <= TIE_CAP || lo == 0) break;
-    lo = lo >= W ? lo - W : 0;
+    const uint32_t got = s_nl;
+    if (got >= (uint32_t)k && got <= (uint32_t)COLLECT_CAP) {
+      int P = 1;
+      while (P < (int)got) P <<= 1;
+      for (int t = got + threadIdx.x; t < P; t += blockDim.x) {
+        bufk[t] = ~0ull;
+        bufd[t] = 0xFFFFFFFFu;
+      }
+      __syncthreads();
+      block_bitonic(bufk, bufd, P);
+      for (int t = threadIdx.x; t < k; t += blockDim.x) {
+        store_key(out_key + row * k + t, bufk[t]);
+        out_doc[row * k + t] = bufd[t];
+      }
+      return;
+    }
+    __syncthreads();  // the buffers are reused below
   }
+
+  // ---- exact path
+  hs = hs0;
+  sel = shr64(mn, hs0);
+  digit_levels(rk, n, (uint32_t)k, (uint32_t)TIE_CAP, hs, sel, below, nties, hist, &s_b, &s_below);
   if (threadIdx.x == 0) s_nl = s_nt = 0;
   __syncthreads();
   const bool many = nties > TIE_CAP;  // then every tie key is the same value
