@@ -27,6 +27,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
 #include <cstdint>
 #include <type_traits>
 
@@ -378,58 +379,183 @@ __device__ __forceinline__ double row_sum_f64(double v) {
 // by the number of matches alone, so a cost does not depend on W, G or the
 // schedule.  The result is valid in wavefront 0.
 template <int C, int W, int G, int VEC>
-__device__ double flow_price(FlowLds<C, W>& L, const int E, const float* __restrict__ X,
+__device__ double flow_price(FlowLds<C, W>& L, const int E, const int nq, const int nd, const float* __restrict__ X,
                              const uint32_t* __restrict__ row_of_rank, const int stride, const int d) {
   constexpr int PER = 64 * W / G;
   constexpr int PV = C * W >= 8 ? 5 : 2;
   using V4 = typename std::conditional<VEC == 4, float4, float>::type;
-  const int tid = threadIdx.x, lane = tid & 63;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int g = tid / G, sub = tid % G;
   const int nv = VEC == 4 ? stride >> 2 : d;
+  const int n = nq + nd;
   double* prod = reinterpret_cast<double*>(L.pp);  // pp and pn are contiguous: 8 * N bytes
-  for (int e0 = 0; e0 < E; e0 += PER) {
-    const int e = e0 + g;
-    const V4* pa = nullptr;
-    const V4* pb = nullptr;
-    uint32_t eta = 0;
-    bool live = false;
-    if (e < E) {
+  if constexpr (C * W < 4) {
+    // short pairs: one match per lane group, in match order
+    for (int e0 = 0; e0 < E; e0 += PER) {
+      const int e = e0 + g;
+      const V4* pa = nullptr;
+      const V4* pb = nullptr;
+      uint32_t eta = 0;
+      bool live = false;
+      if (e < E) {
+        const uint32_t pos = L.em_pos[e];
+        const uint32_t rd = L.rank[pos & 0xFFFFu], rq = L.rank[pos >> 16];
+        eta = L.em_eta[e];
+        live = rd != rq;
+        const int64_t rowd = row_of_rank ? row_of_rank[rd] : rd;
+        const int64_t rowq = row_of_rank ? row_of_rank[rq] : rq;
+        pa = reinterpret_cast<const V4*>(X + rowd * stride);
+        pb = reinterpret_cast<const V4*>(X + rowq * stride);
+      }
+      float acc = 0.0f;
+      for (int v0 = 0; v0 < nv; v0 += G * PV) {
+        V4 xa[PV], xb[PV];
+#pragma unroll
+        for (int t = 0; t < PV; ++t) {
+          const int v = v0 + t * G + sub;
+          const bool in = live && v < nv;
+          xa[t] = in ? pa[v] : V4{};
+          xb[t] = in ? pb[v] : V4{};
+        }
+#pragma unroll
+        for (int t = 0; t < PV; ++t) {
+          if constexpr (VEC == 4) {
+            const float dx = xa[t].x - xb[t].x, dy = xa[t].y - xb[t].y;
+            const float dz = xa[t].z - xb[t].z, dw = xa[t].w - xb[t].w;
+            acc += dx * dx + dy * dy + dz * dz + dw * dw;
+          } else {
+            const float dx = xa[t] - xb[t];
+            acc += dx * dx;
+          }
+        }
+      }
+      acc = group_sum<G>(acc);
+      if (sub == 0 && e < E) prod[e] = live ? (double)eta * (double)sqrtf(acc) : 0.0;
+    }
+  } else {
+    // Matches are priced two at a time that share the item of the smaller
+    // side: a counting sort in LDS (res and slot are free once the matching is
+    // done) groups them by that item, each item's run padded to even length,
+    // and a lane group then reads the shared row once for both (three rows for
+    // two matches).  Products stay indexed by match.  The padded order needs up
+    // to (n - 1) + n / 2 entries (at most n - 1 matches, at most n / 2 odd
+    // runs): slot and the byte array after it (both dead by now) hold 1.5 N.
+    using Lds = FlowLds<C, W>;
+    static_assert(offsetof(Lds, lcn) == offsetof(Lds, slot) + 2 * Lds::N, "slot and lcn must be adjacent");
+    uint32_t* cnt = L.res;
+    uint16_t* ord = L.slot;
+    constexpr uint16_t NONE = 0xFFFFu;
+    const bool by_doc = nd <= nq;
+    for (int i = tid; i < n; i += 64 * W) cnt[i] = 0u;
+    __syncthreads();
+    for (int e = tid; e < E; e += 64 * W) {
       const uint32_t pos = L.em_pos[e];
-      const uint32_t rd = L.rank[pos & 0xFFFFu], rq = L.rank[pos >> 16];
-      eta = L.em_eta[e];
-      live = rd != rq;
-      const int64_t rowd = row_of_rank ? row_of_rank[rd] : rd;
-      const int64_t rowq = row_of_rank ? row_of_rank[rq] : rq;
-      pa = reinterpret_cast<const V4*>(X + rowd * stride);
-      pb = reinterpret_cast<const V4*>(X + rowq * stride);
+      atomicAdd(&cnt[by_doc ? (pos & 0xFFFFu) : (pos >> 16)], 1u);
     }
-    float acc = 0.0f;
-    for (int v0 = 0; v0 < nv; v0 += G * PV) {
-      V4 a[PV], b[PV];
+    __syncthreads();
+    int units;
+    {
+      // exclusive scan of the even-rounded counts: thread t holds [t*C, t*C + C)
+      const int t0 = tid * C;
+      uint32_t v[C], tot = 0;
 #pragma unroll
-      for (int t = 0; t < PV; ++t) {
-        const int v = v0 + t * G + sub;
-        if (live && v < nv) {
-          a[t] = pa[v];
-          b[t] = pb[v];
-        } else {
-          a[t] = b[t] = V4{};
+      for (int c = 0; c < C; ++c) {
+        v[c] = t0 + c < n ? (cnt[t0 + c] + 1u) & ~1u : 0u;
+        tot += v[c];
+      }
+      const uint32_t incl = wave_incl_sum(tot);
+      uint32_t base = incl - tot;
+      uint32_t all = __shfl(incl, 63, 64);
+      if (W > 1) {
+        if (lane == 63) L.x_c[w] = incl;
+        __syncthreads();
+        all = 0;
+        for (int j = 0; j < W; ++j) {
+          if (j < w) base += L.x_c[j];
+          all += L.x_c[j];
         }
       }
 #pragma unroll
-      for (int t = 0; t < PV; ++t) {
-        if constexpr (VEC == 4) {
-          const float dx = a[t].x - b[t].x, dy = a[t].y - b[t].y;
-          const float dz = a[t].z - b[t].z, dw = a[t].w - b[t].w;
-          acc += dx * dx + dy * dy + dz * dz + dw * dw;
-        } else {
-          const float dx = a[t] - b[t];
-          acc += dx * dx;
+      for (int c = 0; c < C; ++c) {
+        if (t0 + c < n) cnt[t0 + c] = base;
+        base += v[c];
+      }
+      units = (int)(all >> 1);
+    }
+    if (2 * units > 3 * FlowLds<C, W>::N / 2) units = 0;  // cannot happen (see above); never overrun
+    for (int i = tid; i < 2 * units; i += 64 * W) ord[i] = NONE;
+    __syncthreads();
+    for (int e = tid; e < E; e += 64 * W) {
+      const uint32_t pos = L.em_pos[e];
+      ord[atomicAdd(&cnt[by_doc ? (pos & 0xFFFFu) : (pos >> 16)], 1u)] = (uint16_t)e;
+    }
+    __syncthreads();
+    for (int u0 = 0; u0 < units; u0 += PER) {
+      const int u = u0 + g;
+      int e1 = E, e2 = E;
+      if (u < units) {
+        e1 = ord[2 * u];  // a run starts at an even slot, so the first is a match
+        const uint16_t o2 = ord[2 * u + 1];
+        e2 = o2 == NONE ? E : (int)o2;
+      }
+      const V4* ps = nullptr;
+      const V4* p1 = nullptr;
+      const V4* p2 = nullptr;
+      uint32_t eta1 = 0, eta2 = 0;
+      bool live1 = false, live2 = false;
+      if (e1 < E) {
+        const uint32_t pos = L.em_pos[e1];
+        const uint32_t rd = L.rank[pos & 0xFFFFu], rq = L.rank[pos >> 16];
+        eta1 = L.em_eta[e1];
+        live1 = rd != rq;
+        const uint32_t rs = by_doc ? rd : rq, ro = by_doc ? rq : rd;
+        const int64_t rows = row_of_rank ? row_of_rank[rs] : rs;
+        const int64_t rowo = row_of_rank ? row_of_rank[ro] : ro;
+        ps = reinterpret_cast<const V4*>(X + rows * stride);
+        p1 = reinterpret_cast<const V4*>(X + rowo * stride);
+      }
+      if (e2 < E) {
+        const uint32_t pos = L.em_pos[e2];
+        const uint32_t rd = L.rank[pos & 0xFFFFu], rq = L.rank[pos >> 16];
+        eta2 = L.em_eta[e2];
+        live2 = rd != rq;
+        const uint32_t ro = by_doc ? rq : rd;
+        const int64_t rowo = row_of_rank ? row_of_rank[ro] : ro;
+        p2 = reinterpret_cast<const V4*>(X + rowo * stride);
+      }
+      const bool lives = live1 || live2;
+      float acc1 = 0.0f, acc2 = 0.0f;
+      for (int v0 = 0; v0 < nv; v0 += G * PV) {
+        V4 xs[PV], x1[PV], x2[PV];
+#pragma unroll
+        for (int t = 0; t < PV; ++t) {
+          const int v = v0 + t * G + sub;
+          const bool in = v < nv;
+          xs[t] = lives && in ? ps[v] : V4{};
+          x1[t] = live1 && in ? p1[v] : V4{};
+          x2[t] = live2 && in ? p2[v] : V4{};
+        }
+#pragma unroll
+        for (int t = 0; t < PV; ++t) {
+          if constexpr (VEC == 4) {
+            float dx = xs[t].x - x1[t].x, dy = xs[t].y - x1[t].y, dz = xs[t].z - x1[t].z, dw = xs[t].w - x1[t].w;
+            acc1 += dx * dx + dy * dy + dz * dz + dw * dw;
+            dx = xs[t].x - x2[t].x, dy = xs[t].y - x2[t].y, dz = xs[t].z - x2[t].z, dw = xs[t].w - x2[t].w;
+            acc2 += dx * dx + dy * dy + dz * dz + dw * dw;
+          } else {
+            const float d1 = xs[t] - x1[t], d2 = xs[t] - x2[t];
+            acc1 += d1 * d1;
+            acc2 += d2 * d2;
+          }
         }
       }
+      acc1 = group_sum<G>(acc1);
+      acc2 = group_sum<G>(acc2);
+      if (sub == 0) {
+        if (e1 < E) prod[e1] = live1 ? (double)eta1 * (double)sqrtf(acc1) : 0.0;
+        if (e2 < E) prod[e2] = live2 ? (double)eta2 * (double)sqrtf(acc2) : 0.0;
+      }
     }
-    acc = group_sum<G>(acc);
-    if (sub == 0 && e < E) prod[e] = live ? (double)eta * (double)sqrtf(acc) : 0.0;
   }
   __syncthreads();
   // a fixed order that depends on E only: lane j of wavefront 0 adds the
