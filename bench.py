@@ -35,10 +35,10 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 # workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a 1 GiB copy
 # (profiles/flowtree_batched_uneven_hbm_traffic.md), valid while the kernel
 # sources hash to TRAFFIC_SOURCES_SHA1.
-TRAFFIC_BYTES = 2.557e11
+TRAFFIC_BYTES = 2.465e+11
 TRAFFIC_SOURCES = ("paper_1910_04126_amd/csrc/flow.h", "paper_1910_04126_amd/csrc/flowtree.hip",
                    "paper_1910_04126_amd/csrc/wave.h", "paper_1910_04126_amd/csrc/common.h")
-TRAFFIC_SOURCES_SHA1 = "cd24ae2e8e666c9a68bff30630285a2479c7844c"
+TRAFFIC_SOURCES_SHA1 = "4e87359a3513a63c664f9624c8f68850386c04b8"
 
 
 def measured_traffic(workload):
