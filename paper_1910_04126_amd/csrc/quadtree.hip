@@ -142,6 +142,10 @@ constexpr int QP_U = 2;          // pieces in flight per wavefront
 constexpr int QP_MAX_PIECES = QP_ENTRIES * (QP_ACC_BYTES / 4) / QP_PIECE;
 
 inline bool post_narrow(int Q, int height) { return Q + height <= 32; }
+// With Q + height <= 31 every key U < 2^(Q + height + 1) once expressed in
+// units of the deepest side 2^(B - height) (S_q, S_d and the counters are
+// multiples of it): the ranking then writes u32 keys.
+inline bool post_compact(int Q, int height) { return Q + height <= 31; }
 
 // Slice size for n docs: at least 8 slices when the docs allow, at most
 // smax docs each.
@@ -229,14 +233,16 @@ __global__ __launch_bounds__(64) void k_post_fill(const int64_t* __restrict__ eo
 // so block b runs on XCD b % 8; slices are given out so that each XCD walks
 // one slice at a time through all the queries of the launch, keeping that
 // slice's lists in its L2.  H: the tree height (narrow counters).
-template <bool NARROW>
+template <bool NARROW, bool COMPACT>
 __global__ __launch_bounds__(QP_THREADS) void k_qt_post(
     const uint2* __restrict__ post, const uint32_t* __restrict__ dir, const uint32_t* __restrict__ cbase,
     int64_t n_cells, int64_t S, int64_t n_sl, const int64_t* __restrict__ d_eoff, const uint64_t* __restrict__ d_S,
     int64_t n_docs, const int64_t* __restrict__ q_eoff, const uint32_t* __restrict__ q_ekey,
     const uint32_t* __restrict__ q_emass, const uint64_t* __restrict__ q_S, int64_t r0, int64_t n_rows, int B, int H,
-    uint64_t* __restrict__ keys, unsigned long long* __restrict__ minmax) {
+    void* __restrict__ keys_out, unsigned long long* __restrict__ minmax) {
+  static_assert(NARROW || !COMPACT, "compact keys need narrow counters");
   using Acc = typename std::conditional<NARROW, uint32_t, unsigned long long>::type;
+  using Key = typename std::conditional<COMPACT, uint32_t, uint64_t>::type;
   constexpr int SMAX = QP_ACC_BYTES / sizeof(Acc);
   __shared__ Acc acc[SMAX];
   __shared__ uint4 items[QP_ENTRIES];          // list start, length, query mass, shift
@@ -314,13 +320,15 @@ __global__ __launch_bounds__(QP_THREADS) void k_qt_post(
     __syncthreads();
   }
   const uint64_t Sq = q_S[q];
-  uint64_t* out = keys + row * n_docs + d0;
+  Key* out = reinterpret_cast<Key*>(keys_out) + row * n_docs + d0;
   const uint64_t* Sd = d_S + d0;
   const int up = NARROW ? B - H : 0;
   unsigned long long mn = ~0ull, mx = 0ull;
   for (int i = tid; i < nd; i += QP_THREADS) {
-    const uint64_t key = Sq + Sd[i] - (((uint64_t)acc[i] << up) << 1);
-    out[i] = key;
+    // compact: in units of 2^(B - H); S_q and S_d are multiples of it
+    const uint64_t key = COMPACT ? ((Sq + Sd[i]) >> up) - ((uint64_t)acc[i] << 1)
+                                 : Sq + Sd[i] - (((uint64_t)acc[i] << up) << 1);
+    out[i] = (Key)key;
     mn = key < mn ? key : mn;
     mx = key > mx ? key : mx;
   }
@@ -453,8 +461,12 @@ extern "C" ft_status ft_quadtree_knn(ft_index* ix, const int64_t* q_off, const u
         FT_REQUIRE(eoff[q + 1] - eoff[q] <= SLOTS_LARGE / 2, FT_ERANGE,
                    "with candidate lists, a query may touch at most 4096 tree cells");
     // query chunks bound the key buffer to about 4 GiB
-    const int64_t rows_per_chunk = std::max<int64_t>(1, std::min<int64_t>(n_q, (int64_t(1) << 29) / n_cols));
-    uint64_t* keys = (uint64_t*)ix->ws_keys.ensure(rows_per_chunk * n_cols * 8);
+    const bool compact = !cand && post_narrow(ix->Q, ix->height) && post_compact(ix->Q, ix->height);
+    const int64_t key_bytes = compact ? 4 : 8;
+    const int64_t rows_per_chunk =
+        std::max<int64_t>(1, std::min<int64_t>(n_q, (int64_t(1) << 32) / key_bytes / n_cols));
+    uint64_t* keys = (uint64_t*)ix->ws_keys.ensure(rows_per_chunk * n_cols * key_bytes);
+    uint32_t* ckey_tmp = compact ? (uint32_t*)ix->ws_tiles.ensure(rows_per_chunk * k * 4) : nullptr;
     if (!cand) prepare_postings(ix, s);
     for (int64_t r0 = 0; r0 < n_q; r0 += rows_per_chunk) {
       const int64_t r1 = std::min(n_q, r0 + rows_per_chunk);
@@ -465,15 +477,16 @@ extern "C" ft_status ft_quadtree_knn(ft_index* ix, const int64_t* q_off, const u
         FT_REQUIRE(groups * 8 * rows < (int64_t(1) << 31), FT_ERANGE, "too many (query, slice) workgroups");
         minmax = (unsigned long long*)ix->ws_sel.ensure(rows_per_chunk * 16);
         k_minmax_init<<<(unsigned)ceil_div(rows, 256), 256, 0, s>>>(minmax, rows);
-        auto go = [&](auto narrow) {
-          k_qt_post<decltype(narrow)::value><<<(unsigned)(groups * 8 * rows), QP_THREADS, 0, s>>>(
+        auto go = [&](auto narrow, auto packed) {
+          k_qt_post<decltype(narrow)::value, decltype(packed)::value><<<(unsigned)(groups * 8 * rows), QP_THREADS, 0, s>>>(
               ix->post.as<uint2>(), ix->post_dir.as<uint32_t>(), ix->post_cbase.as<uint32_t>(), ix->post_cells,
               ix->post_slice, ix->post_nsl, ix->docs.ecnt.as<int64_t>(), ix->docs.S.as<uint64_t>(), n_cols,
               ix->qry.ecnt.as<int64_t>(), ix->qry.ekey.as<uint32_t>(), ix->qry.emass.as<uint32_t>(),
               ix->qry.S.as<uint64_t>(), r0, rows, ix->B, ix->height, keys, minmax);
         };
-        if (post_narrow(ix->Q, ix->height)) go(std::true_type{});
-        else go(std::false_type{});
+        if (compact) go(std::true_type{}, std::true_type{});
+        else if (post_narrow(ix->Q, ix->height)) go(std::true_type{}, std::false_type{});
+        else go(std::false_type{}, std::false_type{});
         FT_HIP(hipGetLastError());
       } else {
         // candidate lists: one query per workgroup, its table in LDS
@@ -502,8 +515,12 @@ extern "C" ft_status ft_quadtree_knn(ft_index* ix, const int64_t* q_off, const u
         FT_HIP(hipGetLastError());
         FT_HIP(hipStreamSynchronize(s));  // the tile table is reused by the next chunk
       }
-      topk_rows(keys, r1 - r0, n_cols, cand ? cand + r0 * n_cols : nullptr, k, out_key + r0 * k, out_doc + r0 * k,
-                s, reinterpret_cast<const uint64_t*>(minmax));
+      if (compact)
+        topk_rows(reinterpret_cast<const uint32_t*>(keys), r1 - r0, n_cols, nullptr, k, out_key + r0 * k,
+                  ix->B - ix->height, out_doc + r0 * k, ckey_tmp, s, reinterpret_cast<const uint64_t*>(minmax));
+      else
+        topk_rows(keys, r1 - r0, n_cols, cand ? cand + r0 * n_cols : nullptr, k, out_key + r0 * k, out_doc + r0 * k,
+                  s, reinterpret_cast<const uint64_t*>(minmax));
     }
   });
 }

@@ -13,6 +13,10 @@ namespace ft {
 // key ([rows][2]).  Launches only.
 void topk_rows(const uint64_t* keys, int64_t rows, int64_t n, const int64_t* docs, int k, uint64_t* out_key,
                int64_t* out_doc, hipStream_t s, const uint64_t* minmax = nullptr);
+// u32 keys in units of 2^shift: the selected keys are written widened,
+// out_key = key << shift (tmp_key: [rows * k] scratch).
+void topk_rows(const uint32_t* keys, int64_t rows, int64_t n, const int64_t* docs, int k, uint64_t* out_key, int shift,
+               int64_t* out_doc, uint32_t* tmp_key, hipStream_t s, const uint64_t* minmax);
 void topk_rows(const float* keys, int64_t rows, int64_t n, const int64_t* docs, int k, float* out_key,
                int64_t* out_doc, hipStream_t s);
 

@@ -11,11 +11,13 @@ namespace ft {
 // Sort keys: 64-bit integer keys, or float32 costs mapped to their bit
 // pattern (non-negative floats order like their bits; -0 is folded to 0).
 __device__ __forceinline__ uint64_t sort_bits(uint64_t k) { return k; }
+__device__ __forceinline__ uint64_t sort_bits(uint32_t k) { return (uint64_t)k; }
 __device__ __forceinline__ uint64_t sort_bits(float c) {
   uint32_t b = __float_as_uint(c);
   return b == 0x80000000u ? 0ull : (uint64_t)b;
 }
 __device__ __forceinline__ void store_key(uint64_t* out, uint64_t b) { *out = b; }
+__device__ __forceinline__ void store_key(uint32_t* out, uint64_t b) { *out = (uint32_t)b; }
 __device__ __forceinline__ void store_key(float* out, uint64_t b) { *out = __uint_as_float((uint32_t)b); }
 
 constexpr int SMALL_MAX = 4096;
@@ -329,6 +331,20 @@ static void topk_rows_impl(const K* keys, int64_t rows, int64_t n, const int64_t
 void topk_rows(const uint64_t* keys, int64_t rows, int64_t n, const int64_t* docs, int k, uint64_t* out_key,
                int64_t* out_doc, hipStream_t s, const uint64_t* minmax) {
   topk_rows_impl<uint64_t>(keys, rows, n, docs, k, out_key, out_doc, minmax, s);
+}
+
+__global__ void k_widen_keys(const uint32_t* __restrict__ in, int64_t n, int shift, uint64_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (uint64_t)in[i] << shift;
+}
+
+void topk_rows(const uint32_t* keys, int64_t rows, int64_t n, const int64_t* docs, int k, uint64_t* out_key, int shift,
+               int64_t* out_doc, uint32_t* tmp_key, hipStream_t s, const uint64_t* minmax) {
+  topk_rows_impl<uint32_t>(keys, rows, n, docs, k, tmp_key, out_doc, minmax, s);
+  if (rows > 0) {
+    k_widen_keys<<<(unsigned)ceil_div(rows * k, 256), 256, 0, s>>>(tmp_key, rows * k, shift, out_key);
+    FT_HIP(hipGetLastError());
+  }
 }
 
 void topk_rows(const float* keys, int64_t rows, int64_t n, const int64_t* docs, int k, float* out_key,
