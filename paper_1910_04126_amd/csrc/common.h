@@ -131,7 +131,8 @@ struct ft_index {
   ft::Dists docs;
   std::vector<int64_t> depth_nodes;  // [height + 1] nodes at each depth
   // inverted doc lists for ranking all docs (built on first use)
-  ft::DevBuf post;         // uint2 [docs.emb_nnz] (doc within slice, cell mass), by slice, then cell
+  ft::DevBuf post;         // u16 [docs.emb_nnz] doc within slice, then (16-byte aligned) u32 [docs.emb_nnz]
+                           // cell mass; by slice, then cell, then doc
   ft::DevBuf post_dir;     // u32 [post_nsl * post_cells] end offset of each cell's list in its slice
   ft::DevBuf post_cbase;   // u32 [32] first cell number of each depth
   int64_t post_slice = 0, post_cells = 0, post_nsl = 0;

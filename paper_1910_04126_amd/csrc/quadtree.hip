@@ -137,7 +137,7 @@ constexpr int QP_WAVES = QP_THREADS / 64;
 constexpr int QP_ACC_BYTES = 32 * 1024;
 constexpr int QP_ENTRIES = 256;  // query cells per round (an item index fits a byte)
 constexpr int QP_PIECE = 256;    // list entries per piece
-constexpr int QP_U = 2;          // pieces in flight per wavefront
+constexpr int QP_U = 4;          // pieces in flight per wavefront
 // a list in a slice has at most one entry per doc
 constexpr int QP_MAX_PIECES = QP_ENTRIES * (QP_ACC_BYTES / 4) / QP_PIECE;
 
@@ -213,16 +213,19 @@ __global__ __launch_bounds__(1024) void k_post_scan(uint32_t* __restrict__ dir, 
 __global__ __launch_bounds__(64) void k_post_fill(const int64_t* __restrict__ eoff, const uint32_t* __restrict__ ekey,
                                                   const uint32_t* __restrict__ emass, int64_t n_docs, int64_t S,
                                                   int64_t n_cells, const uint32_t* __restrict__ cbase,
-                                                  uint32_t* __restrict__ dir, uint2* __restrict__ post) {
+                                                  uint32_t* __restrict__ dir, uint16_t* __restrict__ post_doc,
+                                                  uint32_t* __restrict__ post_mass) {
   const int64_t sl = blockIdx.x;
   const int64_t d0 = sl * S, d1 = d0 + S < n_docs ? d0 + S : n_docs;
   uint32_t* D = dir + sl * n_cells;
-  uint2* P = post + eoff[d0];
+  uint16_t* Pd = post_doc + eoff[d0];
+  uint32_t* Pm = post_mass + eoff[d0];
   for (int64_t d = d0; d < d1; ++d) {
     const uint32_t local = (uint32_t)(d - d0);
     for (int64_t e = eoff[d] + lane_id(); e < eoff[d + 1]; e += 64) {
       const uint32_t pos = atomicAdd(&D[cell_number(cbase, ekey[e])], 1u);
-      P[pos] = make_uint2(local, emass[e]);
+      Pd[pos] = (uint16_t)local;
+      Pm[pos] = emass[e];
     }
     __threadfence();
     __syncthreads();
@@ -235,7 +238,8 @@ __global__ __launch_bounds__(64) void k_post_fill(const int64_t* __restrict__ eo
 // slice's lists in its L2.  H: the tree height (narrow counters).
 template <bool NARROW, bool COMPACT>
 __global__ __launch_bounds__(QP_THREADS) void k_qt_post(
-    const uint2* __restrict__ post, const uint32_t* __restrict__ dir, const uint32_t* __restrict__ cbase,
+    const uint16_t* __restrict__ post_doc, const uint32_t* __restrict__ post_mass, const uint32_t* __restrict__ dir,
+    const uint32_t* __restrict__ cbase,
     int64_t n_cells, int64_t S, int64_t n_sl, const int64_t* __restrict__ d_eoff, const uint64_t* __restrict__ d_S,
     int64_t n_docs, const int64_t* __restrict__ q_eoff, const uint32_t* __restrict__ q_ekey,
     const uint32_t* __restrict__ q_emass, const uint64_t* __restrict__ q_S, int64_t r0, int64_t n_rows, int B, int H,
@@ -260,7 +264,8 @@ __global__ __launch_bounds__(QP_THREADS) void k_qt_post(
   const int nd = (int)(n_docs - d0 < S ? n_docs - d0 : S);
   for (int i = tid; i < nd; i += QP_THREADS) acc[i] = 0;
   const uint32_t* D = dir + sl * n_cells;
-  const uint2* P = post + d_eoff[d0];
+  const uint16_t* Pd = post_doc + d_eoff[d0];
+  const uint32_t* Pm = post_mass + d_eoff[d0];
   const int64_t e0 = q_eoff[q];
   const int ne = (int)(q_eoff[q + 1] - e0);
   const int top = NARROW ? H : B;
@@ -288,14 +293,14 @@ __global__ __launch_bounds__(QP_THREADS) void k_qt_post(
     }
     __syncthreads();
     for (uint32_t p0 = w * QP_U; p0 < n_pieces; p0 += QP_WAVES * QP_U) {
-      uint2 e[QP_U][QP_PIECE / 64];
+      uint32_t ed[QP_U][QP_PIECE / 64], em[QP_U][QP_PIECE / 64];
       uint32_t am[QP_U], sh[QP_U], cnt[QP_U];
 #pragma unroll
       for (int u = 0; u < QP_U; ++u) {
         const uint32_t p = p0 + u;
         cnt[u] = 0;
         am[u] = sh[u] = 0;
-        const uint2* src = P;
+        uint32_t at = 0;
         if (p < n_pieces) {
           const uint32_t it = pitem[p];
           const uint4 item = items[it];
@@ -303,19 +308,20 @@ __global__ __launch_bounds__(QP_THREADS) void k_qt_post(
           cnt[u] = min((uint32_t)QP_PIECE, item.y - off);
           am[u] = item.z;
           sh[u] = item.w;
-          src = P + item.x + off;
+          at = item.x + off;
         }
 #pragma unroll
         for (int j = 0; j < QP_PIECE / 64; ++j) {
           const uint32_t x = j * 64 + lane;
-          e[u][j] = x < cnt[u] ? src[x] : make_uint2(0u, 0u);
+          ed[u][j] = x < cnt[u] ? (uint32_t)Pd[at + x] : 0u;
+          em[u][j] = x < cnt[u] ? Pm[at + x] : 0u;
         }
       }
 #pragma unroll
       for (int u = 0; u < QP_U; ++u)
 #pragma unroll
         for (int j = 0; j < QP_PIECE / 64; ++j)
-          if ((uint32_t)(j * 64 + lane) < cnt[u]) atomicAdd(&acc[e[u][j].x], (Acc)min(am[u], e[u][j].y) << sh[u]);
+          if ((uint32_t)(j * 64 + lane) < cnt[u]) atomicAdd(&acc[ed[u][j]], (Acc)min(am[u], em[u][j]) << sh[u]);
     }
     __syncthreads();
   }
@@ -423,12 +429,17 @@ static void prepare_postings(ft_index* ix, hipStream_t s) {
   FT_HIP(hipMemcpyAsync(cbase, cb, sizeof(cb), hipMemcpyHostToDevice, s));
   uint32_t* dir = (uint32_t*)ix->post_dir.ensure(n_sl * n_cells * 4);
   FT_HIP(hipMemsetAsync(dir, 0, n_sl * n_cells * 4, s));
-  uint2* post = (uint2*)ix->post.ensure(std::max<int64_t>(1, ix->docs.emb_nnz) * sizeof(uint2));
+  // list entries as two arrays: doc within the slice (u16, slices hold at
+  // most 8192 docs) and cell mass (u32), 6 bytes an entry
+  const int64_t ne = std::max<int64_t>(1, ix->docs.emb_nnz);
+  uint16_t* post_doc = (uint16_t*)ix->post.ensure(ne * 6 + 16);
+  uint32_t* post_mass = (uint32_t*)((char*)ix->post.p + ((ne * 2 + 15) & ~int64_t(15)));
   const unsigned g = (unsigned)std::min<int64_t>(n, 1 << 20);
   k_post_count<<<g, 64, 0, s>>>(ix->docs.ecnt.as<int64_t>(), ix->docs.ekey.as<uint32_t>(), n, S, n_cells, cbase, dir);
   k_post_scan<<<(unsigned)n_sl, 1024, 0, s>>>(dir, n_cells);
   k_post_fill<<<(unsigned)n_sl, 64, 0, s>>>(ix->docs.ecnt.as<int64_t>(), ix->docs.ekey.as<uint32_t>(),
-                                            ix->docs.emass.as<uint32_t>(), n, S, n_cells, cbase, dir, post);
+                                            ix->docs.emass.as<uint32_t>(), n, S, n_cells, cbase, dir, post_doc,
+                                            post_mass);
   FT_HIP(hipGetLastError());
   FT_HIP(hipStreamSynchronize(s));
   ix->post_slice = S;
@@ -479,7 +490,9 @@ extern "C" ft_status ft_quadtree_knn(ft_index* ix, const int64_t* q_off, const u
         k_minmax_init<<<(unsigned)ceil_div(rows, 256), 256, 0, s>>>(minmax, rows);
         auto go = [&](auto narrow, auto packed) {
           k_qt_post<decltype(narrow)::value, decltype(packed)::value><<<(unsigned)(groups * 8 * rows), QP_THREADS, 0, s>>>(
-              ix->post.as<uint2>(), ix->post_dir.as<uint32_t>(), ix->post_cbase.as<uint32_t>(), ix->post_cells,
+              ix->post.as<uint16_t>(),
+              (const uint32_t*)((const char*)ix->post.p + ((std::max<int64_t>(1, ix->docs.emb_nnz) * 2 + 15) & ~int64_t(15))),
+              ix->post_dir.as<uint32_t>(), ix->post_cbase.as<uint32_t>(), ix->post_cells,
               ix->post_slice, ix->post_nsl, ix->docs.ecnt.as<int64_t>(), ix->docs.S.as<uint64_t>(), n_cols,
               ix->qry.ecnt.as<int64_t>(), ix->qry.ekey.as<uint32_t>(), ix->qry.emass.as<uint32_t>(),
               ix->qry.S.as<uint64_t>(), r0, rows, ix->B, ix->height, keys, minmax);
