@@ -545,6 +545,10 @@ extern "C" void ft_free(ft_index* ix) {
   if (ix->ev_b) (void)hipEventDestroy(ix->ev_b);
   if (ix->ev_t0) (void)hipEventDestroy(ix->ev_t0);
   if (ix->ev_t1) (void)hipEventDestroy(ix->ev_t1);
+  for (int i = 0; i < 2; ++i) {
+    if (ix->ev_rank[i]) (void)hipEventDestroy(ix->ev_rank[i]);
+    if (ix->ev_sel[i]) (void)hipEventDestroy(ix->ev_sel[i]);
+  }
   if (ix->work) (void)hipStreamDestroy(ix->work);
   delete ix;
 }
@@ -578,6 +582,10 @@ extern "C" ft_status ft_build_tree(const float* X, int64_t V, int32_t d, const i
       FT_HIP(hipEventCreateWithFlags(&ix->ev_b, hipEventDisableTiming));
       FT_HIP(hipEventCreate(&ix->ev_t0));
       FT_HIP(hipEventCreate(&ix->ev_t1));
+      for (int i = 0; i < 2; ++i) {
+        FT_HIP(hipEventCreateWithFlags(&ix->ev_rank[i], hipEventDisableTiming));
+        FT_HIP(hipEventCreateWithFlags(&ix->ev_sel[i], hipEventDisableTiming));
+      }
       ix->status.ensure(64);
       FT_HIP(hipMemsetAsync(ix->status.p, 0, 64, s));
       if (const char* e = getenv("FT_AUTOTUNE")) ix->autotune = atoi(e);

@@ -121,6 +121,7 @@ struct ft_index {
   int n_cu = 0;
   hipStream_t work = nullptr;  // internal stream for graph capture
   hipEvent_t ev_a = nullptr, ev_b = nullptr, ev_t0 = nullptr, ev_t1 = nullptr;
+  hipEvent_t ev_rank[2] = {nullptr, nullptr}, ev_sel[2] = {nullptr, nullptr};  // Quadtree chunk pipeline
   ft::DevBuf Xm;        // float [V * dp], Morton order, rows padded to dp
   ft::DevBuf perm;      // u32 [V] rank -> original id
   ft::DevBuf inv;       // u32 [V] original id -> rank

@@ -476,17 +476,35 @@ extern "C" ft_status ft_quadtree_knn(ft_index* ix, const int64_t* q_off, const u
     const int64_t key_bytes = compact ? 4 : 8;
     const int64_t rows_per_chunk =
         std::max<int64_t>(1, std::min<int64_t>(n_q, (int64_t(1) << 32) / key_bytes / n_cols));
-    uint64_t* keys = (uint64_t*)ix->ws_keys.ensure(rows_per_chunk * n_cols * key_bytes);
+    // Ranking all docs in several chunks runs each chunk's select on the
+    // internal stream while the next chunk is ranked (they are bound by
+    // different units), with two key buffers in turn.
+    const bool pipe = !cand && rows_per_chunk < n_q;
+    const int64_t chunk_bytes = (rows_per_chunk * n_cols * key_bytes + 255) & ~int64_t(255);
+    char* key_base = (char*)ix->ws_keys.ensure(chunk_bytes * (pipe ? 2 : 1));
+    uint64_t* keys = (uint64_t*)key_base;
     uint32_t* ckey_tmp = compact ? (uint32_t*)ix->ws_tiles.ensure(rows_per_chunk * k * 4) : nullptr;
     if (!cand) prepare_postings(ix, s);
-    for (int64_t r0 = 0; r0 < n_q; r0 += rows_per_chunk) {
+    hipStream_t s_sel = pipe ? ix->work : s;
+    if (pipe) {
+      FT_HIP(hipEventRecord(ix->ev_a, s));
+      FT_HIP(hipStreamWaitEvent(s_sel, ix->ev_a, 0));
+    }
+    unsigned long long* minmax_base =
+        cand ? nullptr : (unsigned long long*)ix->ws_sel.ensure(rows_per_chunk * 16 * (pipe ? 2 : 1));
+    int64_t chunk = 0;
+    for (int64_t r0 = 0; r0 < n_q; r0 += rows_per_chunk, ++chunk) {
       const int64_t r1 = std::min(n_q, r0 + rows_per_chunk);
+      const int b = pipe ? (int)(chunk & 1) : 0;
+      keys = (uint64_t*)(key_base + b * chunk_bytes);
       unsigned long long* minmax = nullptr;  // per-row key range, when the ranking kernel gives it
       if (!cand) {
         // all docs: the inverted lists, one workgroup per (query, slice)
         const int64_t rows = r1 - r0, groups = ceil_div(ix->post_nsl, 8);
         FT_REQUIRE(groups * 8 * rows < (int64_t(1) << 31), FT_ERANGE, "too many (query, slice) workgroups");
-        minmax = (unsigned long long*)ix->ws_sel.ensure(rows_per_chunk * 16);
+        minmax = minmax_base + b * rows_per_chunk * 2;
+        // the buffers of chunk - 2 must have been read by its select
+        if (pipe && chunk >= 2) FT_HIP(hipStreamWaitEvent(s, ix->ev_sel[b], 0));
         k_minmax_init<<<(unsigned)ceil_div(rows, 256), 256, 0, s>>>(minmax, rows);
         auto go = [&](auto narrow, auto packed) {
           k_qt_post<decltype(narrow)::value, decltype(packed)::value><<<(unsigned)(groups * 8 * rows), QP_THREADS, 0, s>>>(
@@ -528,12 +546,21 @@ extern "C" ft_status ft_quadtree_knn(ft_index* ix, const int64_t* q_off, const u
         FT_HIP(hipGetLastError());
         FT_HIP(hipStreamSynchronize(s));  // the tile table is reused by the next chunk
       }
+      if (pipe) {
+        FT_HIP(hipEventRecord(ix->ev_rank[b], s));
+        FT_HIP(hipStreamWaitEvent(s_sel, ix->ev_rank[b], 0));
+      }
       if (compact)
         topk_rows(reinterpret_cast<const uint32_t*>(keys), r1 - r0, n_cols, nullptr, k, out_key + r0 * k,
-                  ix->B - ix->height, out_doc + r0 * k, ckey_tmp, s, reinterpret_cast<const uint64_t*>(minmax));
+                  ix->B - ix->height, out_doc + r0 * k, ckey_tmp, s_sel, reinterpret_cast<const uint64_t*>(minmax));
       else
         topk_rows(keys, r1 - r0, n_cols, cand ? cand + r0 * n_cols : nullptr, k, out_key + r0 * k, out_doc + r0 * k,
-                  s, reinterpret_cast<const uint64_t*>(minmax));
+                  s_sel, reinterpret_cast<const uint64_t*>(minmax));
+      if (pipe) FT_HIP(hipEventRecord(ix->ev_sel[b], s_sel));
+    }
+    if (pipe) {
+      FT_HIP(hipEventRecord(ix->ev_b, s_sel));
+      FT_HIP(hipStreamWaitEvent(s, ix->ev_b, 0));
     }
   });
 }
