@@ -13,6 +13,9 @@ candidates afterwards and reported beside it.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload batched|text|image]
        [--no-cpu-baseline] [--no-plain]
+       python bench.py --workload random_model [--reps R]   (the Section 3.2 experiment: success
+                                                              rate of recovering the planted nearest
+                                                              neighbour, Quadtree vs Flowtree, vs N)
        python bench.py --calibrate-copy BYTES   (a plain device copy of BYTES, five times: the
                                                  reference for the HBM byte counters)
 """
@@ -83,9 +86,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0)
+    ap.add_argument("--reps", type=int, default=100)
     args = ap.parse_args()
     if args.calibrate_copy:
         return calibrate_copy(args.calibrate_copy)
+    if args.workload == "random_model":
+        return random_model_experiment(args)
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs on a single MI355X "
               "(the multi-GPU sharding is a design note, not built)", file=sys.stderr)
@@ -217,6 +223,77 @@ def main():
         "cpu_baseline": cpu,
         "index": info,
     }
+    print(json.dumps(out), flush=True)
+
+
+RANDOM_MODEL_SETTINGS = (
+    # (d, s, eps, N values): the two settings of the paper's random-data figure
+    (10, 10, 0.25, (100, 200, 500, 1000, 2000, 5000, 10000)),
+    (10, 100, 0.4, (200, 500, 1000, 2000)),
+)
+
+
+def random_model_experiment(args):
+    """Section 3.2 / 4.1: N points uniform on the sphere, a planted doc of s
+    of them, a query of s points each within eps of its planted point.  The
+    competitors are the planted doc's single-swap neighbours (one x_k
+    replaced by any other of the N points, s * (N - s) docs: the failure
+    event of the analysis is such a swap).  A repetition succeeds for an
+    estimate when the planted doc is strictly the nearest of all; one index
+    and one query per repetition."""
+    if args.gpus != 1:
+        print("bench.py measures one GPU only", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import gen
+    import paper_1910_04126_amd as ft
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    def T(a):
+        a = np.ascontiguousarray(a)
+        if a.dtype == np.uint32:
+            a = a.view(np.int32)
+        return torch.from_numpy(a).to(dev)
+
+    results = []
+    pairs = 0
+    gpu_s = 0.0
+    t_all = time.time()
+    for d, s, eps, Ns in RANDOM_MODEL_SETTINGS:
+        for N in Ns:
+            rng = np.random.default_rng(1000003 * N + 97 * s + d)
+            ok_qt = ok_ft = 0
+            for rep in range(args.reps):
+                ds = gen.random_model_swaps(rng, N, d, s, eps)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                ix = ft.build_tree(T(ds.X), ds.shift, ds.B, T(ds.doc_off), T(ds.doc_id), T(ds.doc_mass), ds.Q)
+                q = (T(ds.q_off), T(ds.q_id), T(ds.q_mass))
+                keys, kd = ft.quadtree_knn(ix, *q, 2)
+                costs, fd = ft.flowtree_knn(ix, *q, 2, mode=ft.FT_PLAIN)
+                torch.cuda.synchronize()
+                gpu_s += time.perf_counter() - t0
+                keys = keys.cpu().numpy().view(np.uint64)[0]
+                costs, kd, fd = costs.cpu().numpy()[0], kd.cpu().numpy()[0], fd.cpu().numpy()[0]
+                ok_qt += int(kd[0] == 0 and keys[0] < keys[1])
+                ok_ft += int(fd[0] == 0 and costs[0] < costs[1])
+                pairs += 2 * ds.n_docs
+                del ix
+            results.append({"d": d, "s": s, "eps": eps, "N": N, "docs": 1 + s * (N - s), "reps": args.reps,
+                             "quadtree_success": ok_qt / args.reps, "flowtree_success": ok_ft / args.reps})
+            log("random model d=%d s=%d eps=%.2f N=%d: quadtree %.2f flowtree %.2f" % (
+                d, s, eps, N, ok_qt / args.reps, ok_ft / args.reps))
+    out = {"metric": "random-model planted nearest neighbour recovered (fraction of repetitions), "
+                     "Quadtree vs Flowtree, as N grows",
+           "unit": "fraction", "higher_is_better": True, "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": "random model of Section 3.2: N uniform points on S^(d-1), planted doc of s "
+                                  "points, query within eps of it; competitors = single-swap docs"},
+           "results": results,
+           "gpu_seconds": round(gpu_s, 2), "wall_seconds": round(time.time() - t_all, 2),
+           "pairs_per_s_incl_index_build": round(pairs / gpu_s, 1)}
     print(json.dumps(out), flush=True)
 
 

@@ -287,6 +287,36 @@ def random_model(rng, N: int, d: int, s: int, eps: float):
     return G, planted.astype(np.uint32), np.arange(N, N + s, dtype=np.uint32)
 
 
+def random_model_swaps(rng, N: int, d: int, s: int, eps: float, Q: int = 24, B: int = None):
+    """One repetition of the random model of Section 3.2, with the planted
+    doc's single-swap neighbours as its competitors.
+
+    Ground set: the N sphere points and the s query points y_k.  Doc 0 is the
+    planted doc (support x_1..x_s); docs 1.. replace one x_k by another of the
+    N points, for every k and every such point: s * (N - s) docs.  Masses
+    follow the support position, floor(2^Q / s) each and one more unit for
+    the first (2^Q mod s) positions, so a swapped point carries exactly the
+    mass of the point it replaces and y_k that of x_k.
+    """
+    B = B_DEFAULT if B is None else B
+    G, planted, qids = random_model(rng, N, d, s, eps)
+    m = np.full(s, (1 << Q) // s, np.uint32)
+    m[: (1 << Q) % s] += 1
+    others = np.setdiff1d(np.arange(N, dtype=np.uint32), planted)
+    n_docs = 1 + s * len(others)
+    ids = np.empty((n_docs, s), np.uint32)
+    ids[0] = planted
+    for k in range(s):
+        blk = ids[1 + k * len(others): 1 + (k + 1) * len(others)]
+        blk[:] = planted
+        blk[:, k] = others
+    doc_off = np.arange(n_docs + 1, dtype=np.int64) * s
+    ds = Dataset("random_model", G, random_shift(rng, d, B), B, Q, doc_off, ids.reshape(-1),
+                 np.tile(m, n_docs), np.array([0, s], np.int64), qids, m.copy(), 2)
+    ds.extra["planted"] = planted
+    return ds
+
+
 # --------------------------------------------------------------------------
 # Workloads
 # --------------------------------------------------------------------------

@@ -417,6 +417,43 @@ def test_invalid_inputs(ft):
     assert torch.isfinite(c).all()
 
 
+# ------------------------------------------------------------ random model --
+
+@pytest.mark.parametrize("N,s,eps,reps", [(100, 10, 0.25, 6), (150, 100, 0.4, 2)])
+def test_random_model_against_oracle(ft, N, s, eps, reps):
+    """The random-model experiment (planted doc against its single-swap
+    neighbours): the top-2 of both estimates and the success flags match
+    the oracle; whenever no smallest common cell H_k of (x_k, y_k) holds
+    another planted point, the Flowtree value of the planted doc is the
+    planted matching's cost (the event of the analysis of Section 3.2)."""
+    rng = np.random.default_rng(77 + N + s)
+    for rep in range(reps):
+        say("random model N=%d s=%d eps=%.2f rep %d" % (N, s, eps, rep))
+        ds = gen.random_model_swaps(rng, N, 10, s, eps)
+        ix = build_index(ft, ds)
+        T = oracle_tree(ds)
+        docs = np.arange(ds.n_docs)
+        keys, kd = ft.quadtree_knn(ix, *queries(ds), 2)
+        costs, fd = ft.flowtree_knn(ix, *queries(ds), 2, mode=ft.FT_PLAIN)
+        M = oracle_matrix(T, ds, [0], docs, "qt")[0]
+        F = oracle_matrix(T, ds, [0], docs, "ft")[0]
+        check_topk(kd[0].cpu().numpy(), keys[0].cpu().numpy().view(np.uint64), M, docs, 2, exact=True)
+        check_topk(fd[0].cpu().numpy(), costs[0].cpu().numpy(), F, docs, 2)
+        x, y = ds.extra["planted"].astype(np.int64), ds.q_id.astype(np.int64)
+        event = True
+        for k in range(s):
+            depth = T.lca_depth(int(x[k]), int(y[k]))
+            if any(T.lca_depth(int(x[j]), int(x[k])) >= depth for j in range(s) if j != k):
+                event = False
+        if event:
+            want = float(np.mean(np.linalg.norm(ds.X[x].astype(np.float64) - ds.X[y].astype(np.float64), axis=1)))
+            c = torch.empty(1, dtype=torch.float32, device="cuda")
+            zero = t(np.zeros(1, np.int64))
+            ft.flowtree_cost_grad(ix, t(ds.X), *queries(ds), zero, zero, ft.FT_FWD, cost=c)
+            got = float(c.cpu().numpy()[0])
+            assert abs(got - want) <= 1e-5 * want, "planted Flowtree %r vs matching cost %r" % (got, want)
+
+
 # ------------------------------------------------------- long-row select --
 
 def test_long_rows_select(ft):
