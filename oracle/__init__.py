@@ -20,6 +20,9 @@ Contents, each following the paper:
   tree and the flow pattern held fixed (the paper gives no gradient; the
   reading is documented with the functions).
 * ``topk``: k smallest by (key, doc id).
+* ``rwmd`` / ``act``: the quadratic-time comparison estimates that follow
+  Flowtree in the paper's pipelines -- Relaxed WMD (Section 1.1) and the
+  Approximate Constrained Transfers with i iterations (Section 4.1), float64.
 
 Parity of the GPU path is judged against these functions.  Functions with no
 independent pin are marked "parity unpinned" in their docstring.
@@ -391,3 +394,66 @@ def frozen_grad(X, mu_id, nu_id, flows, mu_w, nu_w):
         else:
             acc_m[a] += lam
     return gX, acc_m, acc_n
+
+
+# --------------------------------------------------------------------------
+# Relaxed WMD and ACT-i (Section 1.1 "prior work", Section 4.1 baselines)
+# --------------------------------------------------------------------------
+
+def _act_one_way(C, a, b, iters: int) -> float:
+    """One direction of ACT-iters with integer masses a (sources, rows of C)
+    and b (targets, columns).  Each source takes its targets by ascending
+    distance (equal distances by target index); the first ``iters`` of them
+    each receive at most their own mass b_j, and what is left goes to the
+    next nearest target with no limit.  iters = 0 sends everything to the
+    nearest target (one side of R-WMD).  Returns sum of mass x distance in
+    mass units (not yet divided by 2^Q)."""
+    total = 0.0
+    m = C.shape[1]
+    for i in range(C.shape[0]):
+        order = np.argsort(C[i], kind="stable")
+        r = int(a[i])
+        for t in range(min(iters, m)):
+            j = order[t]
+            f = min(r, int(b[j]))
+            total += f * C[i, j]
+            r -= f
+        if iters < m:
+            total += r * C[i, order[iters]]
+        elif r:
+            raise OracleError("ACT: target mass below source mass")
+    return total
+
+
+def act(X, mu_id, mu_m, nu_id, nu_m, Q: int, iters: int) -> float:
+    """ACT-iters estimate of W1(mu, nu) (Section 4.1): the larger of the two
+    one-way capacity-constrained relaxations, each source's mass moved as in
+    ``_act_one_way``; Euclidean costs in float64, masses 2^-Q fixed point.
+    iters = 0 is R-WMD (the paper states the two coincide)."""
+    C = _dist_matrix(X, mu_id, nu_id)
+    a = np.asarray(mu_m, np.int64)
+    b = np.asarray(nu_m, np.int64)
+    fwd = _act_one_way(C, a, b, iters)
+    bwd = _act_one_way(C.T, b, a, iters)
+    return max(fwd, bwd) / float(1 << Q)
+
+
+def rwmd(X, mu_id, mu_m, nu_id, nu_m, Q: int) -> float:
+    """Relaxed WMD (Section 1.1): every support point of one distribution
+    sends its whole mass to its closest support point of the other; the
+    larger of the two directions.  Written directly from that definition
+    (row and column minima of the distance matrix), independent of ``act``."""
+    C = _dist_matrix(X, mu_id, nu_id)
+    a = np.asarray(mu_m, np.float64)
+    b = np.asarray(nu_m, np.float64)
+    return max(float(a @ C.min(axis=1)), float(b @ C.min(axis=0))) / float(1 << Q)
+
+
+def act_pairs(X, q_off, q_id, q_m, d_off, d_id, d_m, pair_q, pair_d, Q: int, iters: int) -> np.ndarray:
+    """``act`` for explicit (query, doc) pairs of CSR sets; float64 [n_pairs]."""
+    out = np.empty(len(pair_q))
+    for p, (q, d) in enumerate(zip(pair_q, pair_d)):
+        qa, qb = q_off[q], q_off[q + 1]
+        da, db = d_off[d], d_off[d + 1]
+        out[p] = act(X, d_id[da:db], d_m[da:db], q_id[qa:qb], q_m[qa:qb], Q, iters)
+    return out
