@@ -38,10 +38,10 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 # workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a 1 GiB copy
 # (profiles/flowtree_batched_uneven_hbm_traffic.md), valid while the kernel
 # sources hash to TRAFFIC_SOURCES_SHA1.
-TRAFFIC_BYTES = 2.465e+11
+TRAFFIC_BYTES = 2.463e+11
 TRAFFIC_SOURCES = ("paper_1910_04126_amd/csrc/flow.h", "paper_1910_04126_amd/csrc/flowtree.hip",
                    "paper_1910_04126_amd/csrc/wave.h", "paper_1910_04126_amd/csrc/common.h")
-TRAFFIC_SOURCES_SHA1 = "4e87359a3513a63c664f9624c8f68850386c04b8"
+TRAFFIC_SOURCES_SHA1 = "85241d086d31de214bbd28b9444928d673fd8e6b"
 
 
 def measured_traffic(workload):
@@ -240,7 +240,10 @@ def random_model_experiment(args):
     replaced by any other of the N points, s * (N - s) docs: the failure
     event of the analysis is such a swap).  A repetition succeeds for an
     estimate when the planted doc is strictly the nearest of all; one index
-    and one query per repetition."""
+    and one query per repetition.  Also reported: how often the planted
+    pair's Flowtree value equals the planted matching's cost (the tree flow
+    is then optimal, which the analysis shows for an event independent of
+    N)."""
     if args.gpus != 1:
         print("bench.py measures one GPU only", file=sys.stderr)
         sys.exit(2)
@@ -265,17 +268,27 @@ def random_model_experiment(args):
     for d, s, eps, Ns in RANDOM_MODEL_SETTINGS:
         for N in Ns:
             rng = np.random.default_rng(1000003 * N + 97 * s + d)
-            ok_qt = ok_ft = 0
+            ok_qt = ok_ft = exact = 0
+            zero = torch.zeros(1, dtype=torch.int64, device=dev)
+            planted_cost = torch.empty(1, dtype=torch.float32, device=dev)
             for rep in range(args.reps):
                 ds = gen.random_model_swaps(rng, N, d, s, eps)
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-                ix = ft.build_tree(T(ds.X), ds.shift, ds.B, T(ds.doc_off), T(ds.doc_id), T(ds.doc_mass), ds.Q)
+                Xd = T(ds.X)
+                ix = ft.build_tree(Xd, ds.shift, ds.B, T(ds.doc_off), T(ds.doc_id), T(ds.doc_mass), ds.Q)
                 q = (T(ds.q_off), T(ds.q_id), T(ds.q_mass))
                 keys, kd = ft.quadtree_knn(ix, *q, 2)
                 costs, fd = ft.flowtree_knn(ix, *q, 2, mode=ft.FT_PLAIN)
                 torch.cuda.synchronize()
                 gpu_s += time.perf_counter() - t0
+                # the planted pair alone: is its Flowtree value the planted
+                # matching's cost (the tree flow optimal, as under the event
+                # of the analysis)?
+                ft.flowtree_cost_grad(ix, Xd, *q, zero, zero, ft.FT_FWD, cost=planted_cost)
+                x, y = ds.X[ds.extra["planted"]].astype(np.float64), ds.X[ds.q_id].astype(np.float64)
+                match = float(np.mean(np.linalg.norm(x - y, axis=1)))
+                exact += int(abs(float(planted_cost.cpu()[0]) - match) <= 1e-5 * match)
                 keys = keys.cpu().numpy().view(np.uint64)[0]
                 costs, kd, fd = costs.cpu().numpy()[0], kd.cpu().numpy()[0], fd.cpu().numpy()[0]
                 ok_qt += int(kd[0] == 0 and keys[0] < keys[1])
@@ -283,9 +296,10 @@ def random_model_experiment(args):
                 pairs += 2 * ds.n_docs
                 del ix
             results.append({"d": d, "s": s, "eps": eps, "N": N, "docs": 1 + s * (N - s), "reps": args.reps,
-                             "quadtree_success": ok_qt / args.reps, "flowtree_success": ok_ft / args.reps})
-            log("random model d=%d s=%d eps=%.2f N=%d: quadtree %.2f flowtree %.2f" % (
-                d, s, eps, N, ok_qt / args.reps, ok_ft / args.reps))
+                             "quadtree_success": ok_qt / args.reps, "flowtree_success": ok_ft / args.reps,
+                             "flowtree_planted_exact": exact / args.reps})
+            log("random model d=%d s=%d eps=%.2f N=%d: quadtree %.2f flowtree %.2f (planted exact %.2f)" % (
+                d, s, eps, N, ok_qt / args.reps, ok_ft / args.reps, exact / args.reps))
     out = {"metric": "random-model planted nearest neighbour recovered (fraction of repetitions), "
                      "Quadtree vs Flowtree, as N grows",
            "unit": "fraction", "higher_is_better": True, "n_gpus": 1, "data": "synthetic",
