@@ -195,6 +195,37 @@ ft_status ft_quadtree_pairs(ft_index* index, const int64_t* q_off, const uint32_
                             const int64_t* pair_d, int64_t n_pairs, uint64_t* out_key,
                             void* stream);
 
+/* ------------------------------------------------------------------------
+ * ft_act_knn -- k nearest dataset distributions by ACT-iters, the capacity
+ * constrained relaxation of W1 (Section 4.1 baseline; iters = 0 is Relaxed
+ * WMD of Section 1.1): for every support point of one distribution, its
+ * iters nearest points of the other each take at most their own mass and
+ * the next nearest takes the rest; the larger of the two directions.
+ * This is the quadratic-time stage the paper's pipelines place after
+ * Flowtree.
+ *
+ * Arguments as ft_flowtree_knn, plus
+ * iters       0..7 (queries larger than 512 points need iters <= 1).
+ * out_cost[n_q*k] float32 2^-Q * sum mass x ||x - y||_2 in the units of X,
+ *             ordered with out_doc by (cost, doc index).
+ * Distances are fp32 in the difference form sqrt(sum (x - y)^2); the
+ * nearest points are found by an fp32 inner-product screen with a rigorous
+ * error bound, so the selection matches the difference form.  Nearest
+ * points at equal distance are taken by ascending Morton rank (the value
+ * does not depend on that order).  Queries up to 2048 points, dataset
+ * distributions up to 65535 points (FT_ERANGE beyond).
+ * ---------------------------------------------------------------------- */
+ft_status ft_act_knn(ft_index* index, const int64_t* q_off, const uint32_t* q_id,
+                     const uint32_t* q_mass, int64_t n_q, const int64_t* cand, int32_t n_cand,
+                     int32_t iters, int32_t k, float* out_cost, int64_t* out_doc, void* stream);
+
+/* ACT-iters values (as ft_act_knn) of explicit pairs: out_cost[n_pairs]
+ * (device float32), pair p = (query pair_q[p], doc pair_d[p]). */
+ft_status ft_act_pairs(ft_index* index, const int64_t* q_off, const uint32_t* q_id,
+                       const uint32_t* q_mass, int64_t n_q, const int64_t* pair_q,
+                       const int64_t* pair_d, int64_t n_pairs, int32_t iters, float* out_cost,
+                       void* stream);
+
 /* Batched-schedule autotuner control.  level 0: fixed default schedule;
  * 1: tune on the first FT_BATCHED call of each workload shape and reuse the
  * winner (the default).  A JSON cache file is read and written at the path

@@ -56,6 +56,8 @@ def load():
         "ft_flowtree_cost_grad": ([p, p, p, p, p, i64, p, p, i64, i32, p, p, p, p, p, p], ctypes.c_int),
         "ft_flowtree_flows": ([p, p, p, p, i64, p, p, i64, p, p, p, p, p, p, p], ctypes.c_int),
         "ft_quadtree_pairs": ([p, p, p, p, i64, p, p, i64, p, p], ctypes.c_int),
+        "ft_act_knn": ([p, p, p, p, i64, p, i32, i32, i32, p, p, p], ctypes.c_int),
+        "ft_act_pairs": ([p, p, p, p, i64, p, p, i64, i32, p, p], ctypes.c_int),
         "ft_set_autotune": ([p, i32], ctypes.c_int),
         "ft_last_batched_stats": ([p, p, p, i32], ctypes.c_int),
     }
@@ -189,6 +191,32 @@ def flowtree_knn(index: Index, q_off, q_id, q_mass, k: int, cand=None, mode: int
     _check(load().ft_flowtree_knn(index.handle, _ptr(q_off), _ptr(q_id), _ptr(q_mass), n_q,
                                   _ptr(cand_t), n_cand, k, mode, _ptr(costs), _ptr(docs), _stream()))
     return costs, docs
+
+
+def act_knn(index: Index, q_off, q_id, q_mass, k: int, iters: int = 1, cand=None):
+    """ft_act_knn -> (costs float32 [n_q, k], docs int64 [n_q, k]); iters = 0
+    is Relaxed WMD."""
+    q_off, q_id, q_mass = _queries(q_off, q_id, q_mass)
+    n_q = q_off.numel() - 1
+    dev = q_off.device
+    cand_t = _i64(cand) if cand is not None else None
+    n_cand = cand_t.shape[-1] if cand_t is not None else 0
+    costs = torch.empty((n_q, k), dtype=torch.float32, device=dev)
+    docs = torch.empty((n_q, k), dtype=torch.int64, device=dev)
+    _check(load().ft_act_knn(index.handle, _ptr(q_off), _ptr(q_id), _ptr(q_mass), n_q,
+                             _ptr(cand_t), n_cand, iters, k, _ptr(costs), _ptr(docs), _stream()))
+    return costs, docs
+
+
+def act_pairs(index: Index, q_off, q_id, q_mass, pair_q, pair_d, iters: int = 1):
+    """ft_act_pairs -> float32 ACT-iters value per pair."""
+    q_off, q_id, q_mass = _queries(q_off, q_id, q_mass)
+    pair_q, pair_d = _i64(pair_q), _i64(pair_d)
+    out = torch.empty(pair_q.numel(), dtype=torch.float32, device=q_off.device)
+    _check(load().ft_act_pairs(index.handle, _ptr(q_off), _ptr(q_id), _ptr(q_mass),
+                               q_off.numel() - 1, _ptr(pair_q), _ptr(pair_d), pair_q.numel(), iters,
+                               _ptr(out), _stream()))
+    return out
 
 
 def quadtree_pairs(index: Index, q_off, q_id, q_mass, pair_q, pair_d):

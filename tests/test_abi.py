@@ -55,6 +55,12 @@ def test_null_arguments_fail_cleanly(lib):
     assert b"NULL" in lib.ft_last_error()
     lib.ft_index_info.restype = ctypes.c_int
     assert lib.ft_index_info(None, None) == -1
+    lib.ft_act_pairs.restype = ctypes.c_int
+    assert lib.ft_act_pairs(None, None, None, None, ctypes.c_int64(0), None, None, ctypes.c_int64(0),
+                            ctypes.c_int32(1), None, None) == -1
+    lib.ft_act_knn.restype = ctypes.c_int
+    assert lib.ft_act_knn(None, None, None, None, ctypes.c_int64(0), None, ctypes.c_int32(0), ctypes.c_int32(1),
+                          ctypes.c_int32(1), None, None, None) == -1
     lib.ft_free(None)
 
 
