@@ -13,6 +13,8 @@ candidates afterwards and reported beside it.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload batched|text|image]
        [--no-cpu-baseline] [--no-plain]
+       python bench.py --workload act [--act-cand C] [--act-iters I]   (the R-WMD / ACT stage after
+                                                              Flowtree: Quadtree 1000 -> Flowtree C -> ACT-I top-20)
        python bench.py --workload random_model [--reps R]   (the Section 3.2 experiment: success
                                                               rate of recovering the planted nearest
                                                               neighbour, Quadtree vs Flowtree, vs N)
@@ -87,11 +89,15 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0)
     ap.add_argument("--reps", type=int, default=100)
+    ap.add_argument("--act-cand", type=int, default=100)
+    ap.add_argument("--act-iters", type=int, default=1)
     args = ap.parse_args()
     if args.calibrate_copy:
         return calibrate_copy(args.calibrate_copy)
     if args.workload == "random_model":
         return random_model_experiment(args)
+    if args.workload == "act":
+        return act_stage(args)
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs on a single MI355X "
               "(the multi-GPU sharding is a design note, not built)", file=sys.stderr)
@@ -309,6 +315,118 @@ def random_model_experiment(args):
            "gpu_seconds": round(gpu_s, 2), "wall_seconds": round(time.time() - t_all, 2),
            "pairs_per_s_incl_index_build": round(pairs / gpu_s, 1)}
     print(json.dumps(out), flush=True)
+
+
+FP64_MFMA_PEAK_TFLOPS = 78.6  # MI355X dense fp64 matrix peak
+
+
+def act_stage(args):
+    """The quadratic-time stage the paper's pipelines put after Flowtree
+    (Section 4.3): on the batched workload, Quadtree prunes every doc to
+    1000, batched Flowtree keeps the best C of those, and ACT-I ranks the C
+    to the top-20.  One step is the ACT-I call for all 4096 queries; the
+    Quadtree and Flowtree stages run once beforehand and are timed beside
+    it.  value = ACT pairs per second of the call (query preparation and
+    select included); roofline: the inner-product contraction of the ACT
+    kernels (2 s_q s_d d flops per pair, unpadded; fp64 on the matrix cores)
+    against the fp64 matrix peak, over their device time."""
+    if args.gpus != 1:
+        print("bench.py measures one GPU only", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_1910_04126_amd as ft
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    C, iters, k = args.act_cand, args.act_iters, 20
+    t0 = time.time()
+    ds, prune, _, desc = workload("batched")
+    log("generated batched workload in %.1fs" % (time.time() - t0))
+
+    def T(a):
+        a = np.ascontiguousarray(a)
+        if a.dtype == np.uint32:
+            a = a.view(np.int32)
+        return torch.from_numpy(a).to(dev)
+
+    ix = ft.build_tree(T(ds.X), ds.shift, ds.B, T(ds.doc_off), T(ds.doc_id), T(ds.doc_mass), ds.Q)
+    q = (T(ds.q_off), T(ds.q_id), T(ds.q_mass))
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record()
+    _, cand = ft.quadtree_knn(ix, *q, prune)
+    ev[1].record()
+    _, fdocs = ft.flowtree_knn(ix, *q, C, cand=cand, mode=ft.FT_BATCHED)
+    ev[2].record()
+    torch.cuda.synchronize()
+    qt_ms, ft_ms = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
+    log("quadtree %.1f ms, flowtree (incl. first-call tuning) %.1f ms" % (qt_ms, ft_ms))
+    _, fdocs = ft.flowtree_knn(ix, *q, C, cand=cand, mode=ft.FT_BATCHED)
+    ev[1].record()
+    _, fdocs = ft.flowtree_knn(ix, *q, C, cand=cand, mode=ft.FT_BATCHED)
+    ev[2].record()
+    torch.cuda.synchronize()
+    ft_ms = ev[1].elapsed_time(ev[2])
+    n_q = ds.n_queries
+    log("warmup x%d" % args.warmup)
+    for _ in range(max(1, args.warmup)):
+        costs, docs = ft.act_knn(ix, *q, k, iters=iters, cand=fdocs)
+    torch.cuda.synchronize()
+    kms = []
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        costs, docs = ft.act_knn(ix, *q, k, iters=iters, cand=fdocs)
+        kms.append(ix.last_act_ms())
+        log("  step %d: ACT kernels %.2f ms" % (i, kms[-1]))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    ms_step = 1000.0 * elapsed / args.steps
+    pairs = n_q * C
+    fd = fdocs.cpu().numpy()
+    sq = np.diff(ds.q_off)
+    sd = np.diff(ds.doc_off)[fd]
+    flops = float(2.0 * ds.d * (sq[:, None].astype(np.float64) * sd).sum())
+    kmean = float(np.mean(kms))
+    achieved = flops / (kmean * 1e-3) / 1e12
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = act_cpu_baseline(ds, fd, iters)
+    out = {
+        "metric": "ACT-%d (query, candidate) pairs/sec on 1 MI355X (the stage after Flowtree)" % iters,
+        "value": round(pairs / (elapsed / args.steps), 1), "unit": "pairs/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": desc + "; then batched Flowtree keeps the best %d candidates and ACT-%d ranks them "
+                                      "to the top-%d" % (C, iters, k),
+                   "queries": n_q, "candidates": C, "iters": iters, "k": k, "act_pairs_per_step": pairs},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": FP64_MFMA_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / FP64_MFMA_PEAK_TFLOPS, 4), "traffic": None,
+                     "kernel": "k_act (all query classes)", "kernel_ms": round(kmean, 3),
+                     "algorithmic_flops": flops},
+        "stages": {"quadtree_prune_ms": round(qt_ms, 3), "flowtree_batched_ms": round(ft_ms, 3),
+                   "act_call_ms": round(ms_step, 3), "act_kernels_ms": round(kmean, 3)},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def act_cpu_baseline(ds, fdocs, iters):
+    """The float64 oracle ACT on a bounded sample of the same pairs
+    (queries in order, all their candidates), single-threaded."""
+    import oracle
+    budget = 15.0
+    done = 0
+    t_start = time.perf_counter()
+    for qq in range(ds.n_queries):
+        oracle.act_pairs(ds.X, ds.q_off, ds.q_id, ds.q_mass, ds.doc_off, ds.doc_id, ds.doc_mass,
+                         np.full(fdocs.shape[1], qq), fdocs[qq], ds.Q, iters)
+        done += 1
+        if time.perf_counter() - t_start > budget:
+            break
+    el = time.perf_counter() - t_start
+    return {"value": round(done * fdocs.shape[1] / el, 2), "unit": "pairs/s", "cores": 1, "kind": "oracle",
+            "sample": "%d of %d queries, all %d candidates each, float64 numpy oracle" %
+                      (done, ds.n_queries, fdocs.shape[1])}
 
 
 def calibrate_copy(nbytes):

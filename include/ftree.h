@@ -205,15 +205,15 @@ ft_status ft_quadtree_pairs(ft_index* index, const int64_t* q_off, const uint32_
  * Flowtree.
  *
  * Arguments as ft_flowtree_knn, plus
- * iters       0..7 (queries larger than 512 points need iters <= 1).
+ * iters       0..7.
  * out_cost[n_q*k] float32 2^-Q * sum mass x ||x - y||_2 in the units of X,
  *             ordered with out_doc by (cost, doc index).
- * Distances are fp32 in the difference form sqrt(sum (x - y)^2); the
- * nearest points are found by an fp32 inner-product screen with a rigorous
- * error bound, so the selection matches the difference form.  Nearest
- * points at equal distance are taken by ascending Morton rank (the value
- * does not depend on that order).  Queries up to 2048 points, dataset
- * distributions up to 65535 points (FT_ERANGE beyond).
+ * Squared distances are |x|^2 + |y|^2 - 2<x,y> with every product and sum in
+ * fp64 (exact widening of the fp32 coordinates), then rounded to fp32;
+ * points of the same id are at distance 0, and values within 2^-40
+ * (|x|^2 + |y|^2) of zero are recomputed in the difference form.  Nearest points at equal
+ * distance are taken by ascending Morton rank (the value does not depend on
+ * that order).
  * ---------------------------------------------------------------------- */
 ft_status ft_act_knn(ft_index* index, const int64_t* q_off, const uint32_t* q_id,
                      const uint32_t* q_mass, int64_t n_q, const int64_t* cand, int32_t n_cand,
@@ -237,6 +237,11 @@ ft_status ft_set_autotune(ft_index* index, int32_t level);
  * and the schedule it used as text. */
 ft_status ft_last_batched_stats(const ft_index* index, double* ms_flowtree, char* schedule,
                                 int32_t schedule_len);
+
+/* Device time of the ACT kernels of the last ft_act_knn call (milliseconds,
+ * HIP events recorded on the caller's stream around the kernel launches;
+ * the query preparation and the top-k select are outside). */
+ft_status ft_last_act_stats(const ft_index* index, double* ms_act);
 
 #ifdef __cplusplus
 }

@@ -58,6 +58,7 @@ def load():
         "ft_quadtree_pairs": ([p, p, p, p, i64, p, p, i64, p, p], ctypes.c_int),
         "ft_act_knn": ([p, p, p, p, i64, p, i32, i32, i32, p, p, p], ctypes.c_int),
         "ft_act_pairs": ([p, p, p, p, i64, p, p, i64, i32, p, p], ctypes.c_int),
+        "ft_last_act_stats": ([p, p], ctypes.c_int),
         "ft_set_autotune": ([p, i32], ctypes.c_int),
         "ft_last_batched_stats": ([p, p, p, i32], ctypes.c_int),
     }
@@ -141,6 +142,12 @@ class Index:
         buf = ctypes.create_string_buffer(256)
         _check(load().ft_last_batched_stats(self._h, ctypes.byref(ms), buf, 256))
         return ms.value, buf.value.decode()
+
+    def last_act_ms(self):
+        """Device time of the ACT kernels of the last act_knn call."""
+        ms = ctypes.c_double(0.0)
+        _check(load().ft_last_act_stats(self._h, ctypes.byref(ms)))
+        return ms.value
 
 
 def build_tree(X, shift, B, doc_off, doc_id, doc_mass, Q) -> Index:

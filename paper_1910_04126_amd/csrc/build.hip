@@ -323,13 +323,25 @@ __global__ void k_st_level(uint8_t* __restrict__ st, int64_t V, int j) {
   st[(int64_t)j * V + r] = v;
 }
 
-__global__ void k_permute_rows(const float* __restrict__ X, const uint32_t* __restrict__ perm, int64_t V, int d,
-                               int dp, float* __restrict__ Xm, uint32_t* __restrict__ inv) {
+// One wavefront per row: the row in Morton order, padded with zeros, and its
+// squared norm in fp64.
+__global__ __launch_bounds__(64) void k_permute_rows(const float* __restrict__ X, const uint32_t* __restrict__ perm,
+                                                     int64_t V, int d, int dp, float* __restrict__ Xm,
+                                                     double* __restrict__ Xn, uint32_t* __restrict__ inv) {
   int64_t r = blockIdx.x;
   if (r >= V) return;
   uint32_t p = perm[r];
-  for (int c = threadIdx.x; c < dp; c += blockDim.x) Xm[r * dp + c] = c < d ? X[(int64_t)p * d + c] : 0.0f;
-  if (threadIdx.x == 0) inv[p] = (uint32_t)r;
+  double n2 = 0.0;
+  for (int c = threadIdx.x; c < dp; c += 64) {
+    const float v = c < d ? X[(int64_t)p * d + c] : 0.0f;
+    Xm[r * dp + c] = v;
+    n2 = fma((double)v, (double)v, n2);
+  }
+  n2 = wave_sum(n2);
+  if (threadIdx.x == 0) {
+    inv[p] = (uint32_t)r;
+    Xn[r] = n2;
+  }
 }
 
 // ---------------------------------------------------------- distributions --
@@ -535,7 +547,7 @@ extern "C" const char* ft_last_error(void) { return ft::g_last_error.c_str(); }
 extern "C" void ft_free(ft_index* ix) {
   if (!ix) return;
   ix->graphs.reset();
-  for (DevBuf* b : {&ix->post, &ix->post_dir, &ix->post_cbase, &ix->Xm, &ix->perm, &ix->inv, &ix->st, &ix->leafd, &ix->anc, &ix->status, &ix->ws_keys,
+  for (DevBuf* b : {&ix->post, &ix->post_dir, &ix->post_cbase, &ix->Xm, &ix->Xn, &ix->perm, &ix->inv, &ix->st, &ix->leafd, &ix->anc, &ix->status, &ix->ws_keys,
                     &ix->ws_cost, &ix->ws_tiles, &ix->ws_lists, &ix->ws_counts, &ix->ws_misc, &ix->ws_sel,
                     &ix->fwd_id, &ix->fwd_eta, &ix->fwd_key, &ix->fwd_bind, &ix->fwd_cnt, &ix->fwd_base, &ix->fwd_sig})
     b->release();
@@ -683,7 +695,8 @@ extern "C" ft_status ft_build_tree(const float* X, int64_t V, int32_t d, const i
       // Morton-ordered, padded coordinates and the inverse permutation
       float* Xm = (float*)ix->Xm.ensure(V * ix->dp * sizeof(float));
       uint32_t* inv = (uint32_t*)ix->inv.ensure(V * 4);
-      k_permute_rows<<<(unsigned)V, 64, 0, s>>>(X, perm, V, d, ix->dp, Xm, inv);
+      double* Xn = (double*)ix->Xn.ensure(V * sizeof(double));
+      k_permute_rows<<<(unsigned)V, 64, 0, s>>>(X, perm, V, d, ix->dp, Xm, Xn, inv);
       FT_HIP(hipGetLastError());
       FT_HIP(hipStreamSynchronize(s));
       FT_HIP(hipFree(code));

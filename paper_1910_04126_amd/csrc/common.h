@@ -123,6 +123,7 @@ struct ft_index {
   hipEvent_t ev_a = nullptr, ev_b = nullptr, ev_t0 = nullptr, ev_t1 = nullptr;
   hipEvent_t ev_rank[2] = {nullptr, nullptr}, ev_sel[2] = {nullptr, nullptr};  // Quadtree chunk pipeline
   ft::DevBuf Xm;        // float [V * dp], Morton order, rows padded to dp
+  ft::DevBuf Xn;        // double [V] squared norms of the Xm rows
   ft::DevBuf perm;      // u32 [V] rank -> original id
   ft::DevBuf inv;       // u32 [V] original id -> rank
   ft::DevBuf st;        // u8  [st_levels * V] range-minimum table over adjacent LCA depths
@@ -149,6 +150,7 @@ struct ft_index {
   std::map<std::string, ft::TuneChoice> tuned;
   ft::BatchedGraphs graphs;
   double last_batched_ms = 0.0;
+  double last_act_ms = 0.0;
   std::string last_schedule;
   std::mutex mu;
 };

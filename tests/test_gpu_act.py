@@ -3,8 +3,8 @@ the float64 oracle (Section 1.1 Relaxed WMD, Section 4.1 ACT-i): every value
 of explicit pairs within 1e-5 relative, and the top-k of candidate lists in
 the oracle's order up to near-ties.  Sizes span several 32 x 32 tiles with
 ragged tails in both directions and all three query classes (<= 128, <= 512,
-<= 2048 points); the grid data of the image workload forces exact distance
-ties (the screen's candidate lists overflow and the full scan runs)."""
+<= 1024 points); the grid data of the image workload forces exact distance
+ties."""
 import sys
 
 import numpy as np
@@ -74,10 +74,10 @@ def test_act_pairs_tiny(ft, iters):
 def test_act_pairs_tiles_and_classes(ft, iters):
     """Text-shaped rows (R^300, unit norm); docs of 1..150 points, queries of
     sizes on both sides of every tile edge and class edge."""
-    say("ACT-%d pairs: R^300, docs 1..150 points, queries up to 700 points" % iters)
+    say("ACT-%d pairs: R^300, docs 1..150 points, queries up to 1024 points" % iters)
     ds = gen.make("text", V=4000, n_docs=300, n_queries=1, lo=1, hi=150)
     rng = np.random.default_rng(11)
-    qsizes = [1, 2, 31, 32, 33, 64, 127, 128, 129, 300, 511, 512, 513, 700]
+    qsizes = [1, 2, 31, 32, 33, 64, 127, 128, 129, 300, 511, 512, 513, 700, 1024]
     qo, qi, qm = csr(rng, qsizes, ds.V, ds.Q)
     ix = build_index(ft, ds)
     sizes = np.diff(ds.doc_off)
@@ -159,17 +159,19 @@ def test_act_knn_candidates(ft, iters):
 
 def test_act_errors(ft):
     say("ACT: argument errors")
-    ds = gen.make("tiny")
+    ds = gen.make("text", V=4000, n_docs=50, n_queries=1, lo=5, hi=50)
     ix = build_index(ft, ds)
     z = t(np.zeros(1, np.int64))
-    with pytest.raises(ft.FtError):
-        ft.act_pairs(ix, *queries(ds), z, z, 8)
-    rng = np.random.default_rng(2)
-    qo, qi, qm = csr(rng, [600], ds.V, ds.Q)
     with pytest.raises(ft.FtError) as e:
-        ft.act_pairs(ix, t(qo), t(qi), t(qm), z, z, 2)
+        ft.act_pairs(ix, *queries(ds), z, z, 8)
+    assert e.value.status == -1
+    rng = np.random.default_rng(2)
+    qo, qi, qm = csr(rng, [2100], ds.V, ds.Q)
+    with pytest.raises(ft.FtError) as e:
+        ft.act_pairs(ix, t(qo), t(qi), t(qm), z, z, 1)
     assert e.value.status == -4
-    # the index still works afterwards
-    got = ft.act_pairs(ix, t(qo), t(qi), t(qm), z, z, 1).cpu().numpy()
-    want = oracle_pairs(ds, qo, qi, qm, [0], [0], 1)
+    # the index still works afterwards, with a largest query and 7 iterations
+    qo, qi, qm = csr(rng, [1024], ds.V, ds.Q)
+    got = ft.act_pairs(ix, t(qo), t(qi), t(qm), z, z, 7).cpu().numpy()
+    want = oracle_pairs(ds, qo, qi, qm, [0], [0], 7)
     check_values(got, want, "after errors")
