@@ -23,6 +23,9 @@ Contents, each following the paper:
 * ``rwmd`` / ``act``: the quadratic-time comparison estimates that follow
   Flowtree in the paper's pipelines -- Relaxed WMD (Section 1.1) and the
   Approximate Constrained Transfers with i iterations (Section 4.1), float64.
+* ``sinkhorn``: Sinkhorn with a fixed small number of iterations (Section
+  4.1, regularisation of Appendix "Sinkhorn regularization parameter"),
+  float64.
 
 Parity of the GPU path is judged against these functions.  Functions with no
 independent pin are marked "parity unpinned" in their docstring.
@@ -456,4 +459,42 @@ def act_pairs(X, q_off, q_id, q_m, d_off, d_id, d_m, pair_q, pair_d, Q: int, ite
         qa, qb = q_off[q], q_off[q + 1]
         da, db = d_off[d], d_off[d + 1]
         out[p] = act(X, d_id[da:db], d_m[da:db], q_id[qa:qb], q_m[qa:qb], Q, iters)
+    return out
+
+
+# --------------------------------------------------------------------------
+# Sinkhorn-k (Section 4.1 baseline; regularisation set per pair, appendix)
+# --------------------------------------------------------------------------
+
+def sinkhorn(X, mu_id, mu_m, nu_id, nu_m, Q: int, iters: int, eta: float = 30.0) -> float:
+    """Sinkhorn-iters estimate of W1(mu, nu), float64.
+
+    Reading: the Gibbs kernel is K = exp(-eta * C / M) with C the Euclidean
+    cost matrix of the pair and M its largest entry (the appendix sets the
+    regularisation from M with eta = 30 on every dataset).  Starting from
+    v = 1, each iteration scales rows then columns, u = a / (K v) and
+    v = b / (K^T u); the estimate is sum_ij u_i K_ij v_j C_ij.  A pair whose
+    costs are all 0 (M = 0) has estimate 0."""
+    C = _dist_matrix(X, mu_id, nu_id)
+    a = np.asarray(mu_m, np.float64) / float(1 << Q)
+    b = np.asarray(nu_m, np.float64) / float(1 << Q)
+    M = C.max()
+    if M == 0.0:
+        return 0.0
+    K = np.exp(-eta * C / M)
+    v = np.ones(len(b))
+    for _ in range(iters):
+        u = a / (K @ v)
+        v = b / (K.T @ u)
+    return float(u @ ((K * C) @ v))
+
+
+def sinkhorn_pairs(X, q_off, q_id, q_m, d_off, d_id, d_m, pair_q, pair_d, Q: int, iters: int,
+                   eta: float = 30.0) -> np.ndarray:
+    """``sinkhorn`` for explicit (query, doc) pairs of CSR sets; float64."""
+    out = np.empty(len(pair_q))
+    for p, (q, d) in enumerate(zip(pair_q, pair_d)):
+        qa, qb = q_off[q], q_off[q + 1]
+        da, db = d_off[d], d_off[d + 1]
+        out[p] = sinkhorn(X, d_id[da:db], d_m[da:db], q_id[qa:qb], q_m[qa:qb], Q, iters, eta)
     return out
