@@ -376,7 +376,7 @@ def act_stage(args):
     t_start = time.perf_counter()
     for i in range(args.steps):
         costs, docs = ft.act_knn(ix, *q, k, iters=iters, cand=fdocs)
-        kms.append(ix.last_act_ms())
+        kms.append(ix.last_rerank_ms())
         log("  step %d: ACT kernels %.2f ms" % (i, kms[-1]))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start

@@ -226,6 +226,36 @@ ft_status ft_act_pairs(ft_index* index, const int64_t* q_off, const uint32_t* q_
                        const int64_t* pair_d, int64_t n_pairs, int32_t iters, float* out_cost,
                        void* stream);
 
+/* ------------------------------------------------------------------------
+ * ft_sinkhorn_knn -- k nearest dataset distributions by Sinkhorn with a
+ * fixed number of iterations (Section 4.1 baseline; the regularisation is
+ * set per pair from its largest cost, as in the appendix): with C the
+ * pair's Euclidean cost matrix and M its largest entry, K = exp(-eta C / M);
+ * from v = 1, each iteration sets u = a / (K v) then v = b / (K^T u); the
+ * estimate is sum_ij u_i K_ij v_j C_ij (0 when M = 0).
+ *
+ * Arguments as ft_flowtree_knn, plus
+ * iters       1..64 (the paper uses 1 and 3);
+ * eta         > 0 (the paper uses 30).
+ * out_cost[n_q*k] float32 estimates in the units of X, ordered with
+ *             out_doc by (cost, doc index).
+ * Costs come from the same fp64 inner-product blocks as ft_act_knn, rounded
+ * to fp32; K is evaluated in fp32, sums in fp64.  Device scratch of up to
+ * 4 GiB (largest doc support x largest query support floats per resident
+ * workgroup) is kept with the index.
+ * ---------------------------------------------------------------------- */
+ft_status ft_sinkhorn_knn(ft_index* index, const int64_t* q_off, const uint32_t* q_id,
+                          const uint32_t* q_mass, int64_t n_q, const int64_t* cand, int32_t n_cand,
+                          int32_t iters, float eta, int32_t k, float* out_cost, int64_t* out_doc,
+                          void* stream);
+
+/* Sinkhorn values (as ft_sinkhorn_knn) of explicit pairs: out_cost[n_pairs]
+ * (device float32), pair p = (query pair_q[p], doc pair_d[p]). */
+ft_status ft_sinkhorn_pairs(ft_index* index, const int64_t* q_off, const uint32_t* q_id,
+                            const uint32_t* q_mass, int64_t n_q, const int64_t* pair_q,
+                            const int64_t* pair_d, int64_t n_pairs, int32_t iters, float eta,
+                            float* out_cost, void* stream);
+
 /* Batched-schedule autotuner control.  level 0: fixed default schedule;
  * 1: tune on the first FT_BATCHED call of each workload shape and reuse the
  * winner (the default).  A JSON cache file is read and written at the path
@@ -238,10 +268,11 @@ ft_status ft_set_autotune(ft_index* index, int32_t level);
 ft_status ft_last_batched_stats(const ft_index* index, double* ms_flowtree, char* schedule,
                                 int32_t schedule_len);
 
-/* Device time of the ACT kernels of the last ft_act_knn call (milliseconds,
- * HIP events recorded on the caller's stream around the kernel launches;
- * the query preparation and the top-k select are outside). */
-ft_status ft_last_act_stats(const ft_index* index, double* ms_act);
+/* Device time of the estimate kernels of the last ft_act_knn or
+ * ft_sinkhorn_knn call (milliseconds, HIP events recorded on the caller's
+ * stream around the kernel launches; the query preparation and the top-k
+ * select are outside). */
+ft_status ft_last_rerank_stats(const ft_index* index, double* ms);
 
 #ifdef __cplusplus
 }

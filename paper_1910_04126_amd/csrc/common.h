@@ -140,7 +140,7 @@ struct ft_index {
   int64_t post_slice = 0, post_cells = 0, post_nsl = 0;
   // per-call workspaces
   ft::Dists qry;
-  ft::DevBuf ws_keys, ws_cost, ws_tiles, ws_lists, ws_counts, ws_misc, ws_sel;
+  ft::DevBuf ws_keys, ws_cost, ws_tiles, ws_lists, ws_counts, ws_misc, ws_sel, ws_rerank;
   ft::DevBuf fwd_id, fwd_eta, fwd_key, fwd_bind, fwd_cnt, fwd_base;  // saved flows (FT_FWD)
   int64_t fwd_pairs = 0, fwd_cap = 0;
   ft::DevBuf fwd_sig;          // copies of the FT_FWD query CSR and pairs
@@ -150,7 +150,7 @@ struct ft_index {
   std::map<std::string, ft::TuneChoice> tuned;
   ft::BatchedGraphs graphs;
   double last_batched_ms = 0.0;
-  double last_act_ms = 0.0;
+  double last_rerank_ms = 0.0;  // device time of the last ACT / Sinkhorn knn kernels
   std::string last_schedule;
   std::mutex mu;
 };

@@ -4,25 +4,12 @@
 // in the paper's pipelines.
 //
 // Per pair, every support point of one side needs its i + 1 nearest points
-// of the other side, in both directions.  All squared distances of a pair
-// come from inner products of its two sets of rows, a dense contraction, on
-// the fp64 matrix cores: D^2 = |x|^2 + |y|^2 - 2 <x, y>, with the fp32
-// coordinates widened exactly and every product and sum in fp64.  That form
-// cancels where x is close to y; in fp64 the cancellation leaves an absolute
-// error near 1e-16 (|x|^2 + |y|^2) on D^2, so the result is rounded to fp32
-// and selected on directly, except for the rare entries within 2^-40
-// (|x|^2 + |y|^2) of zero, which are recomputed in the difference form.
-// Points of the same id are at distance exactly 0.  The capacity walk then
-// runs with integer masses, D = sqrt(D^2) and fp64 products and sums.
-//
-// A 32 x 32 block of the (doc item x query item)
-// matrix is four 16 x 16 tiles of v_mfma_f64_16x16x4_f64, fed straight from
-// L2: per step the four lane groups of 16 take four consecutive float4s of
-// their rows (the contraction order is immaterial), so each load reads 64
-// contiguous bytes of every row it touches.  The block's
-// D^2 goes through LDS; lanes 0..31 then walk its rows (doc items, whose i+1
-// nearest stay in registers across the row of blocks), lanes 32..63 its
-// columns (query items, whose i+1 nearest stay in LDS).
+// of the other side, in both directions.  The squared distances come 32 x 32
+// at a time from the fp64 matrix cores (pairdist.h).  The block's D^2 goes
+// through LDS; lanes 0..31 then walk its rows (doc items, whose i+1 nearest
+// stay in registers across the row of blocks), lanes 32..63 its columns
+// (query items, whose i+1 nearest stay in LDS).  The capacity walk runs with
+// integer masses, D = sqrt(D^2) and fp64 products and sums.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -31,12 +18,11 @@
 
 #include "common.h"
 #include "flow.h"
+#include "pairdist.h"
 #include "select.h"
 #include "wave.h"
 
 namespace ft {
-
-typedef double act_f64x4 __attribute__((ext_vector_type(4)));
 
 struct ActArgs {
   const int64_t* q_off;
@@ -50,10 +36,7 @@ struct ActArgs {
   const int64_t* qlist;   // knn form: the queries of this launch (workgroup b: query qlist[b / n_cols])
   const int64_t* pair_q;  // pairs form: explicit (query, doc) pairs
   const int64_t* pair_d;
-  const float* X;         // Morton-ordered rows, stride dp, padded with zeros
-  const double* Xn;       // their squared norms (fp64)
-  int dp;
-  int NS;                 // float4 steps of 16 coordinates: ceil(dp / 16)
+  PairRows rows;
   int Q;
   int iters;
   uint32_t* status;
@@ -63,9 +46,7 @@ struct ActArgs {
 // K1: how many nearest points an item keeps (a power of two >= iters + 1).
 template <int K1, int QMAX>
 struct ActLds {
-  float tile[32][33];    // D^2 of the current block: [doc item][query item]
-  double nr[32], nc[32]; // squared norms of the block's rows and columns
-  uint32_t rr[32], rc[32];
+  BlockLds blk;
   float cd[K1][QMAX];    // per query item: its K1 smallest D^2 so far, ascending
   uint16_t ci[K1][QMAX]; // and the doc items they belong to
 };
@@ -93,147 +74,6 @@ __device__ __forceinline__ void keep_nearest(float (&v)[K1], int (&ix)[K1], floa
   }
 }
 
-// Inner products of the 16-row halves a0 / a1 (doc rows) with b0 / b1 (query
-// rows) over the full coordinate axis; TA / TB: the second halves exist.
-// Step s: lane group g (lanes 16 g .. 16 g + 15, one row each) takes
-// coordinates 16 s + 4 g .. 16 s + 4 g + 3 of its rows, so each load reads 64
-// contiguous bytes of every row it touches; all steps but the last lie inside
-// the rows, the last is cut at dp.  Rows past the block's items point at a
-// valid row; their results are never read.
-template <bool TA, bool TB>
-__device__ __forceinline__ void block_dots(const float* __restrict__ pa0, const float* __restrict__ pa1,
-                                           const float* __restrict__ pb0, const float* __restrict__ pb1, int NS,
-                                           bool tail_in, act_f64x4& c00, act_f64x4& c01, act_f64x4& c10,
-                                           act_f64x4& c11) {
-  constexpr int PF = 2;
-  float4 x0[PF], x1[PF], y0[PF], y1[PF];
-  const int full = NS - 1;  // steps entirely inside the rows
-  auto issue = [&](int t, int s) {
-    x0[t] = *(const float4*)(pa0 + 16 * s);
-    y0[t] = *(const float4*)(pb0 + 16 * s);
-    if (TA) x1[t] = *(const float4*)(pa1 + 16 * s);
-    if (TB) y1[t] = *(const float4*)(pb1 + 16 * s);
-  };
-  auto step = [&](const float4& xa4, const float4& xb4, const float4& ya4, const float4& yb4) {
-    const float ea[4] = {xa4.x, xa4.y, xa4.z, xa4.w}, eb[4] = {xb4.x, xb4.y, xb4.z, xb4.w};
-    const float fa[4] = {ya4.x, ya4.y, ya4.z, ya4.w}, fb[4] = {yb4.x, yb4.y, yb4.z, yb4.w};
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const double p = ea[c], q = fa[c];
-      c00 = __builtin_amdgcn_mfma_f64_16x16x4f64(p, q, c00, 0, 0, 0);
-      if (TB) c01 = __builtin_amdgcn_mfma_f64_16x16x4f64(p, (double)fb[c], c01, 0, 0, 0);
-      if (TA) c10 = __builtin_amdgcn_mfma_f64_16x16x4f64((double)eb[c], q, c10, 0, 0, 0);
-      if (TA && TB) c11 = __builtin_amdgcn_mfma_f64_16x16x4f64((double)eb[c], (double)fb[c], c11, 0, 0, 0);
-    }
-  };
-  // a ring of PF steps in flight: the steady loop has no conditions, the
-  // ragged end is unrolled with wave-uniform ones
-  int s0 = 0;
-  if (full >= PF) {
-#pragma unroll
-    for (int t = 0; t < PF; ++t) issue(t, t);
-    for (; s0 + 2 * PF <= full; s0 += PF) {
-#pragma unroll
-      for (int t = 0; t < PF; ++t) {
-        step(x0[t], x1[t], y0[t], y1[t]);
-        issue(t, s0 + PF + t);
-      }
-    }
-#pragma unroll
-    for (int t = 0; t < PF; ++t) {
-      step(x0[t], x1[t], y0[t], y1[t]);
-      if (s0 + PF + t < full) issue(t, s0 + PF + t);
-    }
-#pragma unroll
-    for (int t = 0; t < PF; ++t)
-      if (s0 + PF + t < full) step(x0[t], x1[t], y0[t], y1[t]);
-  } else {
-    for (int t = 0; t < full; ++t) {
-      issue(0, t);
-      step(x0[0], x1[0], y0[0], y1[0]);
-    }
-  }
-  // the last step, cut at dp (lanes whose coordinates lie past it add zeros)
-  const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-  const int o = tail_in ? 16 * full : 0;
-  float4 xa = *(const float4*)(pa0 + o), ya = *(const float4*)(pb0 + o);
-  float4 xb = TA ? *(const float4*)(pa1 + o) : z, yb = TB ? *(const float4*)(pb1 + o) : z;
-  if (!tail_in) xa = xb = ya = yb = z;
-  step(xa, xb, ya, yb);
-}
-
-// D^2 of doc items ib.. x query items jb.. into L.tile (32 x 32; entries
-// past ni / nj are not written).
-template <int K1, int QMAX>
-__device__ __forceinline__ void block_d2(ActLds<K1, QMAX>& L, const ActArgs& a, const uint32_t* __restrict__ dr,
-                                         const uint32_t* __restrict__ qr, int ib, int ni, int jb, int nj) {
-  const int lane = threadIdx.x;
-  const int r16 = lane & 15, g = lane >> 4;
-  const bool two_a = ni > 16, two_b = nj > 16;  // wave-uniform: skip empty 16-row halves
-  const uint32_t ra0 = dr[ib + min(r16, ni - 1)], ra1 = dr[ib + min(16 + r16, ni - 1)];
-  const uint32_t rb0 = qr[jb + min(r16, nj - 1)], rb1 = qr[jb + min(16 + r16, nj - 1)];
-  const float* pa0 = a.X + (size_t)ra0 * a.dp + 4 * g;
-  const float* pa1 = a.X + (size_t)ra1 * a.dp + 4 * g;
-  const float* pb0 = a.X + (size_t)rb0 * a.dp + 4 * g;
-  const float* pb1 = a.X + (size_t)rb1 * a.dp + 4 * g;
-  const bool tail_in = 16 * (a.NS - 1) + 4 * g < a.dp;
-  act_f64x4 c00, c01, c10, c11;
-#pragma unroll
-  for (int r = 0; r < 4; ++r) c00[r] = c01[r] = c10[r] = c11[r] = 0.0;
-  if (two_a) {
-    if (two_b) block_dots<true, true>(pa0, pa1, pb0, pb1, a.NS, tail_in, c00, c01, c10, c11);
-    else block_dots<true, false>(pa0, pa1, pb0, pb1, a.NS, tail_in, c00, c01, c10, c11);
-  } else {
-    if (two_b) block_dots<false, true>(pa0, pa1, pb0, pb1, a.NS, tail_in, c00, c01, c10, c11);
-    else block_dots<false, false>(pa0, pa1, pb0, pb1, a.NS, tail_in, c00, c01, c10, c11);
-  }
-  double* nr = L.nr;
-  double* nc = L.nc;
-  uint32_t* rr = L.rr;
-  uint32_t* rc = L.rc;
-  if (lane < 32) {
-    const bool va = lane < ni, vb = lane < nj;
-    const uint32_t ka = va ? dr[ib + lane] : 0u, kb = vb ? qr[jb + lane] : 0u;
-    nr[lane] = va ? a.Xn[ka] : 0.0;
-    nc[lane] = vb ? a.Xn[kb] : 0.0;
-    rr[lane] = va ? ka : 0xFFFFFFFFu;
-    rc[lane] = vb ? kb : 0xFFFFFFFEu;
-  }
-  __syncthreads();
-  float(&tile)[32][33] = L.tile;
-  // 16x16 fp64 result layout: lane l holds column l % 16, rows l / 16 + 4 r
-  auto put = [&](const act_f64x4& c, int i0, int j) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int i = i0 + g + 4 * r;
-      if (i < ni && j < nj) {
-        const double sn = nr[i] + nc[j];
-        const double d2 = sn - 2.0 * c[r];
-        float v = (float)d2;
-        if (rr[i] == rc[j]) {
-          v = 0.0f;
-        } else if (d2 <= 0x1p-40 * sn) {
-          // within the rounding of the inner-product form: the difference
-          // form of the two rows (exact differences, fp64 squares and sum)
-          const float* x = a.X + (size_t)rr[i] * a.dp;
-          const float* y = a.X + (size_t)rc[j] * a.dp;
-          double e = 0.0;
-          for (int k = 0; k < a.dp; ++k) {
-            const double t = (double)x[k] - (double)y[k];
-            e = fma(t, t, e);
-          }
-          v = (float)e;
-        }
-        tile[i][j] = v;
-      }
-    }
-  };
-  put(c00, 0, r16);
-  if (two_b) put(c01, 0, 16 + r16);
-  if (two_a) put(c10, 16, r16);
-  if (two_a && two_b) put(c11, 16, 16 + r16);
-}
-
 // The capacity walk of one item over its K1 nearest points of the other
 // side (ascending D^2): the first `iters` take at most their own mass, the
 // next one takes the rest.  Returns sum mass x distance.
@@ -255,13 +95,6 @@ __device__ __forceinline__ double capacity_walk(const float (&d2)[K1], const int
     }
   }
   return contrib;
-}
-
-// Sum over the wavefront in a fixed order (rows of 16 by DPP, then the four
-// rows), valid in every lane.
-__device__ __forceinline__ double act_wave_sum(double v) {
-  v = row_sum_f64(v);
-  return (__shfl(v, 0, 64) + __shfl(v, 16, 64)) + (__shfl(v, 32, 64) + __shfl(v, 48, 64));
 }
 
 // One wavefront per pair, held to 128 registers (no accumulators in AGPRs)
@@ -315,11 +148,10 @@ __global__ __launch_bounds__(64, 4) void k_act(ActArgs a) {
     }
     for (int jb = 0; jb < nq; jb += 32) {
       const int nj = min(32, nq - jb);
-      block_d2(L, a, dr, qr, ib, ni, jb, nj);
-      __syncthreads();
+      block_d2(L.blk, a.rows, dr, qr, ib, ni, jb, nj);
       if (lane < 32) {
         if (me < ni)
-          for (int x = 0; x < nj; ++x) keep_nearest<K1>(rv, rix, L.tile[me][x], jb + x);
+          for (int x = 0; x < nj; ++x) keep_nearest<K1>(rv, rix, L.blk.tile[me][x], jb + x);
       } else if (me < nj) {
         const int j = jb + me;
         float cv[K1];
@@ -329,7 +161,7 @@ __global__ __launch_bounds__(64, 4) void k_act(ActArgs a) {
           cv[t] = L.cd[t][j];
           cix[t] = L.ci[t][j];
         }
-        for (int x = 0; x < ni; ++x) keep_nearest<K1>(cv, cix, L.tile[x][me], ib + x);
+        for (int x = 0; x < ni; ++x) keep_nearest<K1>(cv, cix, L.blk.tile[x][me], ib + x);
 #pragma unroll
         for (int t = 0; t < K1; ++t) {
           L.cd[t][j] = cv[t];
@@ -339,7 +171,7 @@ __global__ __launch_bounds__(64, 4) void k_act(ActArgs a) {
       __syncthreads();
     }
     const double c = lane < ni ? capacity_walk<K1>(rv, rix, dm[ib + lane], qm, a.iters, nq) : 0.0;
-    tot_d += act_wave_sum(c);
+    tot_d += pair_wave_sum(c);
   }
   double tot_q = 0.0;
   for (int c0 = 0; c0 < nq; c0 += 64) {
@@ -355,7 +187,7 @@ __global__ __launch_bounds__(64, 4) void k_act(ActArgs a) {
       }
       c = capacity_walk<K1>(cv, cix, qm[j], dm, a.iters, nd);
     }
-    tot_q += act_wave_sum(c);
+    tot_q += pair_wave_sum(c);
   }
   if (lane == 0) a.cost[out] = (float)ldexp(tot_d > tot_q ? tot_d : tot_q, -a.Q);
 }
@@ -394,10 +226,7 @@ static ActArgs act_args(ft_index* ix, int32_t iters) {
   a.d_off = ix->docs.off.as<int64_t>();
   a.d_rank = ix->docs.rank.as<uint32_t>();
   a.d_mass = ix->docs.mass.as<uint32_t>();
-  a.X = ix->Xm.as<float>();
-  a.Xn = ix->Xn.as<double>();
-  a.dp = ix->dp;
-  a.NS = (int)ceil_div(ix->dp, 16);
+  a.rows = pair_rows(ix);
   a.Q = ix->Q;
   a.iters = iters;
   a.status = ix->status.as<uint32_t>();
@@ -459,14 +288,14 @@ extern "C" ft_status ft_act_knn(ft_index* ix, const int64_t* q_off, const uint32
     uint32_t flags = read_and_clear_status(ix, s);
     FT_REQUIRE(flags == 0, FT_EHIP, "act kernel reported:" + describe_flags(flags));
     float ms = 0.0f;
-    if (hipEventElapsedTime(&ms, ix->ev_t0, ix->ev_t1) == hipSuccess) ix->last_act_ms = ms;
+    if (hipEventElapsedTime(&ms, ix->ev_t0, ix->ev_t1) == hipSuccess) ix->last_rerank_ms = ms;
   });
 }
 
-extern "C" ft_status ft_last_act_stats(const ft_index* ix, double* ms) {
+extern "C" ft_status ft_last_rerank_stats(const ft_index* ix, double* ms) {
   return guarded([&] {
     FT_REQUIRE(ix && ms, FT_EINVAL, "NULL argument");
-    *ms = ix->last_act_ms;
+    *ms = ix->last_rerank_ms;
   });
 }
 
