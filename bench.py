@@ -15,6 +15,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload batched|t
        [--no-cpu-baseline] [--no-plain]
        python bench.py --workload act [--act-cand C] [--act-iters I]   (the R-WMD / ACT stage after
                                                               Flowtree: Quadtree 1000 -> Flowtree C -> ACT-I top-20)
+       python bench.py --workload sinkhorn [--act-cand C] [--sk-iters I]   (Sinkhorn-I in place of ACT)
        python bench.py --workload random_model [--reps R]   (the Section 3.2 experiment: success
                                                               rate of recovering the planted nearest
                                                               neighbour, Quadtree vs Flowtree, vs N)
@@ -91,13 +92,14 @@ def main():
     ap.add_argument("--reps", type=int, default=100)
     ap.add_argument("--act-cand", type=int, default=100)
     ap.add_argument("--act-iters", type=int, default=1)
+    ap.add_argument("--sk-iters", type=int, default=1)
     args = ap.parse_args()
     if args.calibrate_copy:
         return calibrate_copy(args.calibrate_copy)
     if args.workload == "random_model":
         return random_model_experiment(args)
-    if args.workload == "act":
-        return act_stage(args)
+    if args.workload in ("act", "sinkhorn"):
+        return rerank_stage(args, args.workload)
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs on a single MI355X "
               "(the multi-GPU sharding is a design note, not built)", file=sys.stderr)
@@ -320,16 +322,17 @@ def random_model_experiment(args):
 FP64_MFMA_PEAK_TFLOPS = 78.6  # MI355X dense fp64 matrix peak
 
 
-def act_stage(args):
-    """The quadratic-time stage the paper's pipelines put after Flowtree
+def rerank_stage(args, method):
+    """A quadratic-time stage the paper's pipelines put after Flowtree
     (Section 4.3): on the batched workload, Quadtree prunes every doc to
-    1000, batched Flowtree keeps the best C of those, and ACT-I ranks the C
-    to the top-20.  One step is the ACT-I call for all 4096 queries; the
-    Quadtree and Flowtree stages run once beforehand and are timed beside
-    it.  value = ACT pairs per second of the call (query preparation and
-    select included); roofline: the inner-product contraction of the ACT
-    kernels (2 s_q s_d d flops per pair, unpadded; fp64 on the matrix cores)
-    against the fp64 matrix peak, over their device time."""
+    1000, batched Flowtree keeps the best C of those, and ACT-I (method
+    "act") or Sinkhorn-I ("sinkhorn") ranks the C to the top-20.  One step is
+    that call for all 4096 queries; the Quadtree and Flowtree stages run
+    beforehand and are timed beside it (second calls).  value = pairs per
+    second of the call (query preparation and select included); roofline:
+    the inner-product contraction of the stage's kernels (2 s_q s_d d flops
+    per pair, unpadded; fp64 on the matrix cores) against the fp64 matrix
+    peak, over their device time."""
     if args.gpus != 1:
         print("bench.py measures one GPU only", file=sys.stderr)
         sys.exit(2)
@@ -339,7 +342,14 @@ def act_stage(args):
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    C, iters, k = args.act_cand, args.act_iters, 20
+    C, k = args.act_cand, 20
+    iters = args.act_iters if method == "act" else args.sk_iters
+    name = ("ACT-%d" % iters) if method == "act" else ("Sinkhorn-%d" % iters)
+
+    def call():
+        if method == "act":
+            return ft.act_knn(ix, *q, k, iters=iters, cand=fdocs)
+        return ft.sinkhorn_knn(ix, *q, k, iters=iters, cand=fdocs)
     t0 = time.time()
     ds, prune, _, desc = workload("batched")
     log("generated batched workload in %.1fs" % (time.time() - t0))
@@ -353,6 +363,8 @@ def act_stage(args):
     ix = ft.build_tree(T(ds.X), ds.shift, ds.B, T(ds.doc_off), T(ds.doc_id), T(ds.doc_mass), ds.Q)
     q = (T(ds.q_off), T(ds.q_id), T(ds.q_mass))
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    _, cand = ft.quadtree_knn(ix, *q, prune)
+    _, fdocs = ft.flowtree_knn(ix, *q, C, cand=cand, mode=ft.FT_BATCHED)
     ev[0].record()
     _, cand = ft.quadtree_knn(ix, *q, prune)
     ev[1].record()
@@ -360,24 +372,18 @@ def act_stage(args):
     ev[2].record()
     torch.cuda.synchronize()
     qt_ms, ft_ms = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
-    log("quadtree %.1f ms, flowtree (incl. first-call tuning) %.1f ms" % (qt_ms, ft_ms))
-    _, fdocs = ft.flowtree_knn(ix, *q, C, cand=cand, mode=ft.FT_BATCHED)
-    ev[1].record()
-    _, fdocs = ft.flowtree_knn(ix, *q, C, cand=cand, mode=ft.FT_BATCHED)
-    ev[2].record()
-    torch.cuda.synchronize()
-    ft_ms = ev[1].elapsed_time(ev[2])
+    log("quadtree %.1f ms, flowtree %.1f ms" % (qt_ms, ft_ms))
     n_q = ds.n_queries
     log("warmup x%d" % args.warmup)
     for _ in range(max(1, args.warmup)):
-        costs, docs = ft.act_knn(ix, *q, k, iters=iters, cand=fdocs)
+        costs, docs = call()
     torch.cuda.synchronize()
     kms = []
     t_start = time.perf_counter()
     for i in range(args.steps):
-        costs, docs = ft.act_knn(ix, *q, k, iters=iters, cand=fdocs)
+        costs, docs = call()
         kms.append(ix.last_rerank_ms())
-        log("  step %d: ACT kernels %.2f ms" % (i, kms[-1]))
+        log("  step %d: %s kernels %.2f ms" % (i, name, kms[-1]))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     ms_step = 1000.0 * elapsed / args.steps
@@ -390,36 +396,38 @@ def act_stage(args):
     achieved = flops / (kmean * 1e-3) / 1e12
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = act_cpu_baseline(ds, fd, iters)
+        cpu = rerank_cpu_baseline(ds, fd, method, iters)
     out = {
-        "metric": "ACT-%d (query, candidate) pairs/sec on 1 MI355X (the stage after Flowtree)" % iters,
+        "metric": "%s (query, candidate) pairs/sec on 1 MI355X (the stage after Flowtree)" % name,
         "value": round(pairs / (elapsed / args.steps), 1), "unit": "pairs/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": desc + "; then batched Flowtree keeps the best %d candidates and ACT-%d ranks them "
-                                      "to the top-%d" % (C, iters, k),
+        "config": {"workload": desc + "; then batched Flowtree keeps the best %d candidates and %s ranks them "
+                                      "to the top-%d" % (C, name, k),
                    "queries": n_q, "candidates": C, "iters": iters, "k": k, "act_pairs_per_step": pairs},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": FP64_MFMA_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / FP64_MFMA_PEAK_TFLOPS, 4), "traffic": None,
-                     "kernel": "k_act (all query classes)", "kernel_ms": round(kmean, 3),
+                     "kernel": "k_act (all query classes)" if method == "act" else "k_sinkhorn",
+                     "kernel_ms": round(kmean, 3),
                      "algorithmic_flops": flops},
         "stages": {"quadtree_prune_ms": round(qt_ms, 3), "flowtree_batched_ms": round(ft_ms, 3),
-                   "act_call_ms": round(ms_step, 3), "act_kernels_ms": round(kmean, 3)},
+                   "rerank_call_ms": round(ms_step, 3), "rerank_kernels_ms": round(kmean, 3)},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 
 
-def act_cpu_baseline(ds, fdocs, iters):
-    """The float64 oracle ACT on a bounded sample of the same pairs
-    (queries in order, all their candidates), single-threaded."""
+def rerank_cpu_baseline(ds, fdocs, method, iters):
+    """The float64 oracle (ACT or Sinkhorn) on a bounded sample of the same
+    pairs (queries in order, all their candidates), single-threaded."""
     import oracle
+    f = oracle.act_pairs if method == "act" else oracle.sinkhorn_pairs
     budget = 15.0
     done = 0
     t_start = time.perf_counter()
     for qq in range(ds.n_queries):
-        oracle.act_pairs(ds.X, ds.q_off, ds.q_id, ds.q_mass, ds.doc_off, ds.doc_id, ds.doc_mass,
-                         np.full(fdocs.shape[1], qq), fdocs[qq], ds.Q, iters)
+        f(ds.X, ds.q_off, ds.q_id, ds.q_mass, ds.doc_off, ds.doc_id, ds.doc_mass,
+          np.full(fdocs.shape[1], qq), fdocs[qq], ds.Q, iters)
         done += 1
         if time.perf_counter() - t_start > budget:
             break

@@ -55,7 +55,33 @@ struct SinkLds {
   float v[FT_MAX_SUPPORT];  // column scalings (query items)
 };
 
-__global__ __launch_bounds__(64, 4) void k_sinkhorn(SinkArgs a) {
+constexpr int SR = 4;  // rows summed together
+
+// Sums over j of K_ij v_j (WITH_D: times D_ij) for rows i0 .. i0 + SR - 1
+// (rows past nd give 0): lanes across the row, then a fixed-order wavefront
+// sum per row; the result is valid in every lane.
+template <bool WITH_D>
+__device__ __forceinline__ void row_sums(const float* __restrict__ S, int nq, int nd, int i0, float cexp,
+                                         const float* __restrict__ v, double (&acc)[SR]) {
+  const int lane = threadIdx.x;
+#pragma unroll
+  for (int r = 0; r < SR; ++r) acc[r] = 0.0;
+  for (int j = lane; j < nq; j += 64) {
+    float d[SR];
+#pragma unroll
+    for (int r = 0; r < SR; ++r) d[r] = i0 + r < nd ? S[(int64_t)(i0 + r) * nq + j] : 0.0f;
+    const float vj = v[j];
+#pragma unroll
+    for (int r = 0; r < SR; ++r) {
+      const double t = (double)(exp2f(cexp * d[r]) * vj);
+      acc[r] += WITH_D ? t * (double)d[r] : t;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < SR; ++r) acc[r] = i0 + r < nd ? pair_wave_sum(acc[r]) : 0.0;
+}
+
+__global__ __launch_bounds__(64) void k_sinkhorn(SinkArgs a) {
   __shared__ SinkLds L;
   const int lane = threadIdx.x;
   float* S = a.scratch + (int64_t)blockIdx.x * a.slot;
@@ -107,30 +133,42 @@ __global__ __launch_bounds__(64, 4) void k_sinkhorn(SinkArgs a) {
       for (int j = lane; j < nq; j += 64) L.v[j] = 1.0f;
       __syncthreads();
       for (int it = 0; it < a.iters; ++it) {
-        for (int i = 0; i < nd; ++i) {
-          const float* row = S + (int64_t)i * nq;
-          double acc = 0.0;
-          for (int j = lane; j < nq; j += 64) acc += (double)(exp2f(cexp * row[j]) * L.v[j]);
-          acc = pair_wave_sum(acc);
-          if (lane == 0) L.u[i] = (float)((double)dm[i] * scale / acc);
+        // rows, SR at a time (their loads and sums interleave): u = a / (K v)
+        for (int i0 = 0; i0 < nd; i0 += SR) {
+          double acc[SR];
+          row_sums<false>(S, nq, nd, i0, cexp, L.v, acc);
+          if (lane < SR && i0 + lane < nd) {
+            double mine = acc[0];
+#pragma unroll
+            for (int r = 1; r < SR; ++r)
+              if (lane == r) mine = acc[r];
+            L.u[i0 + lane] = (float)((double)dm[i0 + lane] * scale / mine);
+          }
         }
         __syncthreads();
+        // columns, one lane each: v = b / (K^T u)
         for (int j = lane; j < nq; j += 64) {
           double acc = 0.0;
-          for (int i = 0; i < nd; ++i) acc += (double)(exp2f(cexp * S[(int64_t)i * nq + j]) * L.u[i]);
+          int i = 0;
+          for (; i + 8 <= nd; i += 8) {
+            float d[8];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) d[r] = S[(int64_t)(i + r) * nq + j];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) acc += (double)(exp2f(cexp * d[r]) * L.u[i + r]);
+          }
+          for (; i < nd; ++i) acc += (double)(exp2f(cexp * S[(int64_t)i * nq + j]) * L.u[i]);
           L.v[j] = (float)((double)qm[j] * scale / acc);
         }
         __syncthreads();
       }
-      for (int i = 0; i < nd; ++i) {
-        const float* row = S + (int64_t)i * nq;
-        double acc = 0.0;
-        for (int j = lane; j < nq; j += 64) {
-          const float d = row[j];
-          acc += (double)(exp2f(cexp * d) * L.v[j]) * (double)d;
-        }
-        acc = pair_wave_sum(acc);
-        est += (double)L.u[i] * acc;
+      // the estimate: sum_i u_i sum_j K_ij v_j D_ij, rows in order
+      for (int i0 = 0; i0 < nd; i0 += SR) {
+        double acc[SR];
+        row_sums<true>(S, nq, nd, i0, cexp, L.v, acc);
+#pragma unroll
+        for (int r = 0; r < SR; ++r)
+          if (i0 + r < nd) est += (double)L.u[i0 + r] * acc[r];
       }
     }
     if (lane == 0) a.cost[p] = (float)est;
@@ -153,13 +191,16 @@ static SinkArgs sink_args(ft_index* ix, int32_t iters, float eta) {
   return a;
 }
 
-// Persistent grid: as many workgroups as fit (12 per CU at this LDS size),
-// fewer when the slots would pass 4 GiB.
+// Persistent grid: as many workgroups as are resident at once (pairs are
+// dealt to them by stride, so none may wait for a slot), fewer when the
+// slots would pass 4 GiB.
 static void launch_sinkhorn(ft_index* ix, SinkArgs a, hipStream_t s) {
   if (a.n_pairs <= 0) return;
   a.slot = std::max<int64_t>(1, (int64_t)ix->docs.max_size * ix->qry.max_size);
   const int64_t budget = int64_t(1) << 30;  // floats
-  int64_t grid = std::min<int64_t>((int64_t)ix->n_cu * 12, a.n_pairs);
+  int per_cu = 0;
+  FT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sinkhorn, 64, 0));
+  int64_t grid = std::min<int64_t>((int64_t)ix->n_cu * std::max(1, per_cu), a.n_pairs);
   grid = std::max<int64_t>(1, std::min<int64_t>(grid, budget / a.slot));
   a.scratch = (float*)ix->ws_rerank.ensure((size_t)(grid * a.slot) * sizeof(float));
   k_sinkhorn<<<dim3((unsigned)grid), 64, 0, s>>>(a);
