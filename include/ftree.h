@@ -256,6 +256,31 @@ ft_status ft_sinkhorn_pairs(ft_index* index, const int64_t* q_off, const uint32_
                             const int64_t* pair_d, int64_t n_pairs, int32_t iters, float eta,
                             float* out_cost, void* stream);
 
+/* ------------------------------------------------------------------------
+ * ft_exact_knn -- k nearest dataset distributions by the exact W1 distance
+ * (Section 1, eq. (1): the cheapest transport of one distribution onto the
+ * other at Euclidean cost), the last stage of the paper's pipelines.
+ *
+ * Arguments as ft_flowtree_knn.
+ * out_cost[n_q*k] float32 W1 in the units of X, ordered with out_doc by
+ *             (cost, doc index).
+ * Each pair is solved exactly by successive shortest paths with node
+ * potentials on the fp32 distance matrix (from the fp64 inner-product
+ * blocks of ft_act_knn) with the integer masses; the value is summed in
+ * fp64.  Cost grows with the pair sizes (quadratic per shortest path):
+ * meant for a few candidates per query.  Device scratch of up to 4 GiB is
+ * kept with the index.
+ * ---------------------------------------------------------------------- */
+ft_status ft_exact_knn(ft_index* index, const int64_t* q_off, const uint32_t* q_id,
+                       const uint32_t* q_mass, int64_t n_q, const int64_t* cand, int32_t n_cand,
+                       int32_t k, float* out_cost, int64_t* out_doc, void* stream);
+
+/* Exact W1 (as ft_exact_knn) of explicit pairs: out_cost[n_pairs] (device
+ * float32), pair p = (query pair_q[p], doc pair_d[p]). */
+ft_status ft_exact_pairs(ft_index* index, const int64_t* q_off, const uint32_t* q_id,
+                         const uint32_t* q_mass, int64_t n_q, const int64_t* pair_q,
+                         const int64_t* pair_d, int64_t n_pairs, float* out_cost, void* stream);
+
 /* Batched-schedule autotuner control.  level 0: fixed default schedule;
  * 1: tune on the first FT_BATCHED call of each workload shape and reuse the
  * winner (the default).  A JSON cache file is read and written at the path
@@ -268,8 +293,8 @@ ft_status ft_set_autotune(ft_index* index, int32_t level);
 ft_status ft_last_batched_stats(const ft_index* index, double* ms_flowtree, char* schedule,
                                 int32_t schedule_len);
 
-/* Device time of the estimate kernels of the last ft_act_knn or
- * ft_sinkhorn_knn call (milliseconds, HIP events recorded on the caller's
+/* Device time of the kernels of the last ft_act_knn, ft_sinkhorn_knn or
+ * ft_exact_knn call (milliseconds, HIP events recorded on the caller's
  * stream around the kernel launches; the query preparation and the top-k
  * select are outside). */
 ft_status ft_last_rerank_stats(const ft_index* index, double* ms);

@@ -59,6 +59,8 @@ def load():
         "ft_act_knn": ([p, p, p, p, i64, p, i32, i32, i32, p, p, p], ctypes.c_int),
         "ft_act_pairs": ([p, p, p, p, i64, p, p, i64, i32, p, p], ctypes.c_int),
         "ft_last_rerank_stats": ([p, p], ctypes.c_int),
+        "ft_exact_knn": ([p, p, p, p, i64, p, i32, i32, p, p, p], ctypes.c_int),
+        "ft_exact_pairs": ([p, p, p, p, i64, p, p, i64, p, p], ctypes.c_int),
         "ft_sinkhorn_knn": ([p, p, p, p, i64, p, i32, i32, ctypes.c_float, i32, p, p, p], ctypes.c_int),
         "ft_sinkhorn_pairs": ([p, p, p, p, i64, p, p, i64, i32, ctypes.c_float, p, p], ctypes.c_int),
         "ft_set_autotune": ([p, i32], ctypes.c_int),
@@ -251,6 +253,31 @@ def sinkhorn_pairs(index: Index, q_off, q_id, q_mass, pair_q, pair_d, iters: int
     _check(load().ft_sinkhorn_pairs(index.handle, _ptr(q_off), _ptr(q_id), _ptr(q_mass),
                                     q_off.numel() - 1, _ptr(pair_q), _ptr(pair_d), pair_q.numel(), iters, eta,
                                     _ptr(out), _stream()))
+    return out
+
+
+def exact_knn(index: Index, q_off, q_id, q_mass, k: int, cand=None):
+    """ft_exact_knn -> (W1 float32 [n_q, k], docs int64 [n_q, k])."""
+    q_off, q_id, q_mass = _queries(q_off, q_id, q_mass)
+    n_q = q_off.numel() - 1
+    dev = q_off.device
+    cand_t = _i64(cand) if cand is not None else None
+    n_cand = cand_t.shape[-1] if cand_t is not None else 0
+    costs = torch.empty((n_q, k), dtype=torch.float32, device=dev)
+    docs = torch.empty((n_q, k), dtype=torch.int64, device=dev)
+    _check(load().ft_exact_knn(index.handle, _ptr(q_off), _ptr(q_id), _ptr(q_mass), n_q,
+                               _ptr(cand_t), n_cand, k, _ptr(costs), _ptr(docs), _stream()))
+    return costs, docs
+
+
+def exact_pairs(index: Index, q_off, q_id, q_mass, pair_q, pair_d):
+    """ft_exact_pairs -> float32 exact W1 per pair."""
+    q_off, q_id, q_mass = _queries(q_off, q_id, q_mass)
+    pair_q, pair_d = _i64(pair_q), _i64(pair_d)
+    out = torch.empty(pair_q.numel(), dtype=torch.float32, device=q_off.device)
+    _check(load().ft_exact_pairs(index.handle, _ptr(q_off), _ptr(q_id), _ptr(q_mass),
+                                 q_off.numel() - 1, _ptr(pair_q), _ptr(pair_d), pair_q.numel(), _ptr(out),
+                                 _stream()))
     return out
 
 

@@ -9,7 +9,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["build.hip", "select.hip", "quadtree.hip", "flowtree.hip", "grad.hip", "relaxed.hip", "sinkhorn.hip"]
+SOURCES = ["build.hip", "select.hip", "quadtree.hip", "flowtree.hip", "grad.hip", "relaxed.hip", "sinkhorn.hip", "exact.hip"]
 LIB = os.path.join(HERE, "libftree.so")
 ARCH = os.environ.get("FT_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",

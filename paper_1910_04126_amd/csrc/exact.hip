@@ -1,0 +1,358 @@
+// Exact W1 (paper Section 1, eq. (1): the optimal transport cost under the
+// Euclidean metric) for (query, candidate) pairs -- the last stage of the
+// paper's pipelines, run on the few candidates the estimates leave.
+//
+// Per pair, a transportation problem between the doc items (supplies, the
+// integer masses) and the query items (demands), solved exactly by
+// successive shortest paths with node potentials (the primal-dual method):
+// each round runs Dijkstra from every item that still has supply over the
+// residual graph (forward edges doc -> query always, backward edges where a
+// flow is positive), with costs reduced by the potentials so that every
+// residual edge costs >= 0, stops at the first query item with unmet
+// demand, pushes the largest amount the path allows, and moves the
+// potentials by the distances.  Masses and flows are integers, so every
+// round ends at least one supply, demand or backward flow, and the flow at
+// the end is optimal for the fp32 distance matrix; the value is summed in
+// fp64.
+//
+// One wavefront per pair, persistent over the pairs with a scratch slot per
+// workgroup: the distance matrix (fp32, row per doc item, from the fp64
+// matrix-core blocks of pairdist.h) and the flow (u32, row per query item,
+// so that the backward edges into a query item are contiguous).  Dijkstra
+// keeps its arrays in LDS: each step takes the nearest unvisited node by a
+// wavefront arg-min (ties: query items first, then the lower index) and
+// relaxes its edges with the lanes across the other side.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "common.h"
+#include "pairdist.h"
+#include "select.h"
+#include "wave.h"
+
+namespace ft {
+
+struct ExactArgs {
+  const int64_t* q_off;
+  const uint32_t* q_rank;
+  const uint32_t* q_mass;
+  const int64_t* d_off;
+  const uint32_t* d_rank;
+  const uint32_t* d_mass;
+  const int64_t* cand;    // knn form: [n_q * n_cols] doc per (query, column), or NULL (column = doc)
+  int64_t n_cols;
+  const int64_t* pair_q;  // pairs form: explicit (query, doc) pairs
+  const int64_t* pair_d;
+  int64_t n_pairs;
+  PairRows rows;
+  int Q;
+  float* scratch;         // gridDim.x slots of 2 * `slot` words: distances, then flows
+  int64_t slot;
+  uint32_t* status;
+  float* cost;            // knn form: [query * n_cols + column]; pairs form: [pair]
+};
+
+constexpr uint16_t EX_NONE = 0xFFFF;
+
+struct ExactLds {
+  BlockLds blk;
+  double ps[FT_MAX_SUPPORT], pt[FT_MAX_SUPPORT];  // potentials: doc items, query items
+  double ds[FT_MAX_SUPPORT], dt[FT_MAX_SUPPORT];  // Dijkstra distances (reduced costs)
+  uint32_t es[FT_MAX_SUPPORT], et[FT_MAX_SUPPORT];  // supply / demand not yet moved
+  uint16_t prs[FT_MAX_SUPPORT], prt[FT_MAX_SUPPORT];  // predecessor on the other side
+  uint8_t vs[FT_MAX_SUPPORT], vt[FT_MAX_SUPPORT];  // settled
+  uint32_t delta;  // the round's push, for every lane
+};
+
+// Wavefront arg-min of (distance, key); the winner is valid in every lane.
+__device__ __forceinline__ void argmin_dist(double& d, uint32_t& key) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double od = __shfl_xor(d, o, 64);
+    const uint32_t ok = __shfl_xor(key, o, 64);
+    if (od < d || (od == d && ok < key)) {
+      d = od;
+      key = ok;
+    }
+  }
+}
+
+__global__ __launch_bounds__(64) void k_exact(ExactArgs a) {
+  __shared__ ExactLds L;
+  const int lane = threadIdx.x;
+  float* S = a.scratch + (int64_t)blockIdx.x * 2 * a.slot;
+  uint32_t* F = (uint32_t*)(S + a.slot);
+  for (int64_t p = blockIdx.x; p < a.n_pairs; p += gridDim.x) {
+    int64_t q, doc;
+    if (a.pair_q) {
+      q = a.pair_q[p];
+      doc = a.pair_d[p];
+    } else {
+      q = p / a.n_cols;
+      const int64_t c = p - q * a.n_cols;
+      doc = a.cand ? a.cand[p] : c;
+    }
+    const int64_t qa = a.q_off[q], da = a.d_off[doc];
+    const int nq = __builtin_amdgcn_readfirstlane((int)(a.q_off[q + 1] - qa));
+    const int nd = __builtin_amdgcn_readfirstlane((int)(a.d_off[doc + 1] - da));
+    if ((int64_t)nq * nd > a.slot) {  // the host sizes the slots; never taken
+      if (lane == 0) atomicOr(a.status, ERR_SIZE);
+      continue;
+    }
+    const uint32_t* dr = a.d_rank + da;
+    const uint32_t* dm = a.d_mass + da;
+    const uint32_t* qr = a.q_rank + qa;
+    const uint32_t* qm = a.q_mass + qa;
+    // distances D[i][j] (row per doc item), zero flows F[j][i] (row per query item)
+    for (int ib = 0; ib < nd; ib += 32) {
+      const int ni = min(32, nd - ib);
+      for (int jb = 0; jb < nq; jb += 32) {
+        const int nj = min(32, nq - jb);
+        block_d2(L.blk, a.rows, dr, qr, ib, ni, jb, nj);
+        const int col = lane & 31;
+        for (int r = lane >> 5; r < ni; r += 2)
+          if (col < nj) S[(int64_t)(ib + r) * nq + jb + col] = sqrtf(L.blk.tile[r][col]);
+        __syncthreads();
+      }
+    }
+    for (int64_t e = lane; e < (int64_t)nq * nd; e += 64) F[e] = 0u;
+    for (int i = lane; i < nd; i += 64) {
+      L.ps[i] = 0.0;
+      L.es[i] = dm[i];
+    }
+    for (int j = lane; j < nq; j += 64) {
+      L.pt[j] = 0.0;
+      L.et[j] = qm[j];
+    }
+    __syncthreads();
+    uint32_t left = 1u << a.Q;  // mass still to move
+    const int64_t max_rounds = 16 * (int64_t)(nd + nq) + 4096;
+    bool failed = false;
+    for (int64_t round = 0; left > 0; ++round) {
+      if (round >= max_rounds) {  // cannot happen for valid masses; flagged, not looped on
+        failed = true;
+        break;
+      }
+      // Dijkstra from every doc item with supply left
+      for (int i = lane; i < nd; i += 64) {
+        L.ds[i] = L.es[i] > 0 ? 0.0 : INFINITY;
+        L.prs[i] = EX_NONE;
+        L.vs[i] = 0;
+      }
+      for (int j = lane; j < nq; j += 64) {
+        L.dt[j] = INFINITY;
+        L.prt[j] = EX_NONE;
+        L.vt[j] = 0;
+      }
+      __syncthreads();
+      int target = -1;
+      double dist_t = 0.0;
+      while (true) {
+        // nearest unvisited node; key: query items (bit 16 clear) before doc items
+        double bd = INFINITY;
+        uint32_t bk = 0xFFFFFFFFu;
+        for (int j = lane; j < nq; j += 64)
+          if (!L.vt[j] && L.dt[j] < bd) {
+            bd = L.dt[j];
+            bk = (uint32_t)j;
+          }
+        for (int i = lane; i < nd; i += 64)
+          if (!L.vs[i] && (L.ds[i] < bd || (L.ds[i] == bd && (0x10000u | (uint32_t)i) < bk))) {
+            bd = L.ds[i];
+            bk = 0x10000u | (uint32_t)i;
+          }
+        argmin_dist(bd, bk);
+        if (bd == INFINITY) {  // no path to unmet demand: cannot happen for valid masses
+          failed = true;
+          break;
+        }
+        if (!(bk & 0x10000u)) {
+          const int j = (int)bk;
+          if (lane == 0) L.vt[j] = 1;
+          if (L.et[j] > 0) {
+            target = j;
+            dist_t = bd;
+            __syncthreads();
+            break;
+          }
+          // backward edges j -> i where the flow (i, j) is positive
+          const uint32_t* Fj = F + (int64_t)j * nd;
+          const double pj = L.pt[j];
+          for (int i = lane; i < nd; i += 64) {
+            if (!L.vs[i] && Fj[i] > 0u) {
+              const double rc = -((double)S[(int64_t)i * nq + j] + L.ps[i] - pj);
+              const double nd2 = bd + (rc > 0.0 ? rc : 0.0);
+              if (nd2 < L.ds[i]) {
+                L.ds[i] = nd2;
+                L.prs[i] = (uint16_t)j;
+              }
+            }
+          }
+        } else {
+          const int i = (int)(bk & 0xFFFFu);
+          if (lane == 0) L.vs[i] = 1;
+          const float* Di = S + (int64_t)i * nq;
+          const double pi = L.ps[i];
+          for (int j = lane; j < nq; j += 64) {
+            if (!L.vt[j]) {
+              const double rc = (double)Di[j] + pi - L.pt[j];
+              const double nd2 = bd + (rc > 0.0 ? rc : 0.0);
+              if (nd2 < L.dt[j]) {
+                L.dt[j] = nd2;
+                L.prt[j] = (uint16_t)i;
+              }
+            }
+          }
+        }
+        __syncthreads();
+      }
+      if (failed) break;
+      // the amount the path allows, then the push (one lane walks the path)
+      if (lane == 0) {
+        uint32_t delta = min(L.et[target], left);
+        int j = target;
+        while (true) {
+          const int i = L.prt[j];
+          const int jb = L.prs[i];
+          if (jb == EX_NONE) {
+            delta = min(delta, L.es[i]);
+            break;
+          }
+          delta = min(delta, F[(int64_t)jb * nd + i]);
+          j = jb;
+        }
+        j = target;
+        while (true) {
+          const int i = L.prt[j];
+          F[(int64_t)j * nd + i] += delta;
+          const int jb = L.prs[i];
+          if (jb == EX_NONE) {
+            L.es[i] -= delta;
+            break;
+          }
+          F[(int64_t)jb * nd + i] -= delta;
+          j = jb;
+        }
+        L.et[target] -= delta;
+        L.delta = delta;
+      }
+      __syncthreads();
+      left -= L.delta;
+      // potentials move by the distances, capped at the target's (nodes not
+      // settled are at least that far)
+      for (int i = lane; i < nd; i += 64) L.ps[i] += fmin(L.ds[i], dist_t);
+      for (int j = lane; j < nq; j += 64) L.pt[j] += fmin(L.dt[j], dist_t);
+      __syncthreads();
+    }
+    // the flow's cost, rows of query items in order
+    double acc = 0.0;
+    if (!failed) {
+      for (int j = 0; j < nq; ++j) {
+        double t = 0.0;
+        for (int i = lane; i < nd; i += 64) {
+          const uint32_t f = F[(int64_t)j * nd + i];
+          if (f) t += (double)f * (double)S[(int64_t)i * nq + j];
+        }
+        acc += pair_wave_sum(t);
+      }
+    } else if (lane == 0) {
+      atomicOr(a.status, ERR_FLOW);
+    }
+    if (lane == 0) a.cost[p] = failed ? NAN : (float)ldexp(acc, -a.Q);
+    __syncthreads();
+  }
+}
+
+static ExactArgs exact_args(ft_index* ix) {
+  ExactArgs a{};
+  a.q_rank = ix->qry.rank.as<uint32_t>();
+  a.q_mass = ix->qry.mass.as<uint32_t>();
+  a.d_off = ix->docs.off.as<int64_t>();
+  a.d_rank = ix->docs.rank.as<uint32_t>();
+  a.d_mass = ix->docs.mass.as<uint32_t>();
+  a.rows = pair_rows(ix);
+  a.Q = ix->Q;
+  a.status = ix->status.as<uint32_t>();
+  return a;
+}
+
+// Persistent grid: as many workgroups as are resident at once, fewer when
+// the slots (distances and flows) would pass 4 GiB.
+static void launch_exact(ft_index* ix, ExactArgs a, hipStream_t s) {
+  if (a.n_pairs <= 0) return;
+  a.slot = std::max<int64_t>(1, (int64_t)ix->docs.max_size * ix->qry.max_size);
+  const int64_t budget = int64_t(1) << 30;  // words
+  int per_cu = 0;
+  FT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_exact, 64, 0));
+  int64_t grid = std::min<int64_t>((int64_t)ix->n_cu * std::max(1, per_cu), a.n_pairs);
+  grid = std::max<int64_t>(1, std::min<int64_t>(grid, budget / (2 * a.slot)));
+  a.scratch = (float*)ix->ws_rerank.ensure((size_t)(grid * 2 * a.slot) * sizeof(float));
+  k_exact<<<dim3((unsigned)grid), 64, 0, s>>>(a);
+  FT_HIP(hipGetLastError());
+}
+
+}  // namespace ft
+
+using namespace ft;
+
+extern "C" ft_status ft_exact_knn(ft_index* ix, const int64_t* q_off, const uint32_t* q_id, const uint32_t* q_mass,
+                                  int64_t n_q, const int64_t* cand, int32_t n_cand, int32_t k, float* out_cost,
+                                  int64_t* out_doc, void* stream) {
+  return guarded([&] {
+    FT_REQUIRE(ix && out_cost && out_doc, FT_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lock(ix->mu);
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n_cols = cand ? (int64_t)n_cand : ix->docs.n;
+    FT_REQUIRE(!cand || (n_cand >= 1 && n_cand <= 4096), FT_ERANGE, "n_cand must lie in [1, 4096]");
+    FT_REQUIRE(k >= 1 && k <= n_cols, FT_EINVAL, "k must lie in [1, number of candidates]");
+    FT_REQUIRE(n_cols <= 4096 || k <= 1024, FT_ERANGE, "k > 1024 needs at most 4096 candidates");
+    prepare_dists(ix, ix->qry, q_off, q_id, q_mass, n_q, false, s, "queries");
+    if (cand) check_indices(ix, cand, n_q * n_cand, ix->docs.n, s, "cand");
+    const int64_t rows = std::max<int64_t>(1, std::min<int64_t>(n_q, (int64_t(1) << 28) / n_cols));
+    float* cost = (float*)ix->ws_cost.ensure(rows * n_cols * 4);
+    for (int64_t r0 = 0; r0 < n_q; r0 += rows) {
+      const int64_t r1 = std::min(n_q, r0 + rows);
+      ExactArgs a = exact_args(ix);
+      a.q_off = ix->qry.off.as<int64_t>() + r0;
+      a.cand = cand ? cand + r0 * n_cols : nullptr;
+      a.n_cols = n_cols;
+      a.n_pairs = (r1 - r0) * n_cols;
+      a.cost = cost;
+      if (r0 == 0) FT_HIP(hipEventRecord(ix->ev_t0, s));
+      launch_exact(ix, a, s);
+      if (r1 == n_q) FT_HIP(hipEventRecord(ix->ev_t1, s));
+      topk_rows(cost, r1 - r0, n_cols, a.cand, k, out_cost + r0 * k, out_doc + r0 * k, s);
+    }
+    uint32_t flags = read_and_clear_status(ix, s);
+    FT_REQUIRE(flags == 0, FT_EHIP, "exact kernel reported:" + describe_flags(flags));
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, ix->ev_t0, ix->ev_t1) == hipSuccess) ix->last_rerank_ms = ms;
+  });
+}
+
+extern "C" ft_status ft_exact_pairs(ft_index* ix, const int64_t* q_off, const uint32_t* q_id, const uint32_t* q_mass,
+                                    int64_t n_q, const int64_t* pair_q, const int64_t* pair_d, int64_t n_pairs,
+                                    float* out_cost, void* stream) {
+  return guarded([&] {
+    FT_REQUIRE(ix && pair_q && pair_d && out_cost, FT_EINVAL, "NULL argument");
+    FT_REQUIRE(n_pairs >= 0, FT_EINVAL, "n_pairs must be >= 0");
+    std::lock_guard<std::mutex> lock(ix->mu);
+    hipStream_t s = (hipStream_t)stream;
+    prepare_dists(ix, ix->qry, q_off, q_id, q_mass, n_q, false, s, "queries");
+    if (n_pairs == 0) return;
+    check_indices(ix, pair_q, n_pairs, n_q, s, "pair_q");
+    check_indices(ix, pair_d, n_pairs, ix->docs.n, s, "pair_d");
+    ExactArgs a = exact_args(ix);
+    a.q_off = ix->qry.off.as<int64_t>();
+    a.pair_q = pair_q;
+    a.pair_d = pair_d;
+    a.n_pairs = n_pairs;
+    a.cost = out_cost;
+    launch_exact(ix, a, s);
+    uint32_t flags = read_and_clear_status(ix, s);
+    FT_REQUIRE(flags == 0, FT_EHIP, "exact kernel reported:" + describe_flags(flags));
+  });
+}
