@@ -16,6 +16,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload batched|t
        python bench.py --workload act [--act-cand C] [--act-iters I]   (the R-WMD / ACT stage after
                                                               Flowtree: Quadtree 1000 -> Flowtree C -> ACT-I top-20)
        python bench.py --workload sinkhorn [--act-cand C] [--sk-iters I]   (Sinkhorn-I in place of ACT)
+       python bench.py --workload exact [--act-cand C]   (exact W1 of the best C by Flowtree, C = 20)
        python bench.py --workload random_model [--reps R]   (the Section 3.2 experiment: success
                                                               rate of recovering the planted nearest
                                                               neighbour, Quadtree vs Flowtree, vs N)
@@ -90,7 +91,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0)
     ap.add_argument("--reps", type=int, default=100)
-    ap.add_argument("--act-cand", type=int, default=100)
+    ap.add_argument("--act-cand", type=int, default=0)
     ap.add_argument("--act-iters", type=int, default=1)
     ap.add_argument("--sk-iters", type=int, default=1)
     args = ap.parse_args()
@@ -98,7 +99,7 @@ def main():
         return calibrate_copy(args.calibrate_copy)
     if args.workload == "random_model":
         return random_model_experiment(args)
-    if args.workload in ("act", "sinkhorn"):
+    if args.workload in ("act", "sinkhorn", "exact"):
         return rerank_stage(args, args.workload)
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs on a single MI355X "
@@ -342,14 +343,17 @@ def rerank_stage(args, method):
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    C, k = args.act_cand, 20
+    C = args.act_cand or (20 if method == "exact" else 100)
+    k = 5 if method == "exact" else 20
     iters = args.act_iters if method == "act" else args.sk_iters
-    name = ("ACT-%d" % iters) if method == "act" else ("Sinkhorn-%d" % iters)
+    name = {"act": "ACT-%d" % iters, "sinkhorn": "Sinkhorn-%d" % iters, "exact": "exact W1"}[method]
 
     def call():
         if method == "act":
             return ft.act_knn(ix, *q, k, iters=iters, cand=fdocs)
-        return ft.sinkhorn_knn(ix, *q, k, iters=iters, cand=fdocs)
+        if method == "sinkhorn":
+            return ft.sinkhorn_knn(ix, *q, k, iters=iters, cand=fdocs)
+        return ft.exact_knn(ix, *q, k, cand=fdocs)
     t0 = time.time()
     ds, prune, _, desc = workload("batched")
     log("generated batched workload in %.1fs" % (time.time() - t0))
@@ -407,7 +411,8 @@ def rerank_stage(args, method):
                    "queries": n_q, "candidates": C, "iters": iters, "k": k, "act_pairs_per_step": pairs},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": FP64_MFMA_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / FP64_MFMA_PEAK_TFLOPS, 4), "traffic": None,
-                     "kernel": "k_act (all query classes)" if method == "act" else "k_sinkhorn",
+                     "kernel": {"act": "k_act (all query classes)", "sinkhorn": "k_sinkhorn",
+                                "exact": "k_exact"}[method],
                      "kernel_ms": round(kmean, 3),
                      "algorithmic_flops": flops},
         "stages": {"quadtree_prune_ms": round(qt_ms, 3), "flowtree_batched_ms": round(ft_ms, 3),
@@ -418,23 +423,29 @@ def rerank_stage(args, method):
 
 
 def rerank_cpu_baseline(ds, fdocs, method, iters):
-    """The float64 oracle (ACT or Sinkhorn) on a bounded sample of the same
+    """The float64 oracle (ACT, Sinkhorn or exact W1) on a bounded sample of the same
     pairs (queries in order, all their candidates), single-threaded."""
     import oracle
-    f = oracle.act_pairs if method == "act" else oracle.sinkhorn_pairs
     budget = 15.0
     done = 0
     t_start = time.perf_counter()
     for qq in range(ds.n_queries):
-        f(ds.X, ds.q_off, ds.q_id, ds.q_mass, ds.doc_off, ds.doc_id, ds.doc_mass,
-          np.full(fdocs.shape[1], qq), fdocs[qq], ds.Q, iters)
+        pq, pd = np.full(fdocs.shape[1], qq), fdocs[qq]
+        if method == "exact":
+            for d in pd:
+                a, b = ds.doc_off[d], ds.doc_off[d + 1]
+                qa, qb = ds.q_off[qq], ds.q_off[qq + 1]
+                oracle.exact_w1_lp(ds.X, ds.doc_id[a:b], ds.doc_mass[a:b], ds.q_id[qa:qb], ds.q_mass[qa:qb], ds.Q)
+        else:
+            f = oracle.act_pairs if method == "act" else oracle.sinkhorn_pairs
+            f(ds.X, ds.q_off, ds.q_id, ds.q_mass, ds.doc_off, ds.doc_id, ds.doc_mass, pq, pd, ds.Q, iters)
         done += 1
         if time.perf_counter() - t_start > budget:
             break
     el = time.perf_counter() - t_start
     return {"value": round(done * fdocs.shape[1] / el, 2), "unit": "pairs/s", "cores": 1, "kind": "oracle",
-            "sample": "%d of %d queries, all %d candidates each, float64 numpy oracle" %
-                      (done, ds.n_queries, fdocs.shape[1])}
+            "sample": "%d of %d queries, all %d candidates each, float64 oracle (%s)" %
+                      (done, ds.n_queries, fdocs.shape[1], "LP by HiGHS" if method == "exact" else "numpy")}
 
 
 def calibrate_copy(nbytes):

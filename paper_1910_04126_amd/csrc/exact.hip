@@ -19,9 +19,13 @@
 // workgroup: the distance matrix (fp32, row per doc item, from the fp64
 // matrix-core blocks of pairdist.h) and the flow (u32, row per query item,
 // so that the backward edges into a query item are contiguous).  Dijkstra
-// keeps its arrays in LDS: each step takes the nearest unvisited node by a
-// wavefront arg-min (ties: query items first, then the lower index) and
-// relaxes its edges with the lanes across the other side.
+// keeps its arrays in LDS and runs level by level: each step finds the
+// smallest distance among unsettled nodes (a wavefront min), ends if a
+// query item with unmet demand is at it (the lowest such index), else
+// settles every node at that distance at once and relaxes their edges with
+// the lanes across the other side (ties between predecessors: the first in
+// the level's order).  After the potentials move, many nodes share a
+// distance, so a round takes few steps.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -67,17 +71,16 @@ struct ExactLds {
   uint32_t delta;  // the round's push, for every lane
 };
 
-// Wavefront arg-min of (distance, key); the winner is valid in every lane.
-__device__ __forceinline__ void argmin_dist(double& d, uint32_t& key) {
+__device__ __forceinline__ double wave_min_f64(double v) {
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const double od = __shfl_xor(d, o, 64);
-    const uint32_t ok = __shfl_xor(key, o, 64);
-    if (od < d || (od == d && ok < key)) {
-      d = od;
-      key = ok;
-    }
-  }
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o, 64));
+  return v;
 }
 
 __global__ __launch_bounds__(64) void k_exact(ExactArgs a) {
@@ -150,62 +153,90 @@ __global__ __launch_bounds__(64) void k_exact(ExactArgs a) {
       __syncthreads();
       int target = -1;
       double dist_t = 0.0;
+      // the nodes settled at one distance level (ids), in the block tile,
+      // free after the distance pass
+      uint16_t* bs = reinterpret_cast<uint16_t*>(&L.blk.tile[0][0]);
+      uint16_t* bt = bs + FT_MAX_SUPPORT;
       while (true) {
-        // nearest unvisited node; key: query items (bit 16 clear) before doc items
+        // the level: the smallest distance of a node not yet settled
         double bd = INFINITY;
-        uint32_t bk = 0xFFFFFFFFu;
         for (int j = lane; j < nq; j += 64)
-          if (!L.vt[j] && L.dt[j] < bd) {
-            bd = L.dt[j];
-            bk = (uint32_t)j;
-          }
+          if (!L.vt[j] && L.dt[j] < bd) bd = L.dt[j];
         for (int i = lane; i < nd; i += 64)
-          if (!L.vs[i] && (L.ds[i] < bd || (L.ds[i] == bd && (0x10000u | (uint32_t)i) < bk))) {
-            bd = L.ds[i];
-            bk = 0x10000u | (uint32_t)i;
-          }
-        argmin_dist(bd, bk);
+          if (!L.vs[i] && L.ds[i] < bd) bd = L.ds[i];
+        bd = wave_min_f64(bd);
         if (bd == INFINITY) {  // no path to unmet demand: cannot happen for valid masses
           failed = true;
           break;
         }
-        if (!(bk & 0x10000u)) {
-          const int j = (int)bk;
-          if (lane == 0) L.vt[j] = 1;
-          if (L.et[j] > 0) {
-            target = j;
-            dist_t = bd;
-            __syncthreads();
-            break;
-          }
-          // backward edges j -> i where the flow (i, j) is positive
-          const uint32_t* Fj = F + (int64_t)j * nd;
+        // a query item with unmet demand at this level ends the search
+        uint32_t tj = 0xFFFFFFFFu;
+        for (int j = lane; j < nq; j += 64)
+          if (!L.vt[j] && L.dt[j] == bd && L.et[j] > 0 && (uint32_t)j < tj) tj = (uint32_t)j;
+        tj = wave_min_u32(tj);
+        if (tj != 0xFFFFFFFFu) {
+          target = (int)tj;
+          dist_t = bd;
+          break;
+        }
+        // settle every node of the level, then relax from all of them
+        int cs = 0, ct = 0;
+        for (int i = lane; i < nd; i += 64) cs += (!L.vs[i] && L.ds[i] == bd) ? 1 : 0;
+        for (int j = lane; j < nq; j += 64) ct += (!L.vt[j] && L.dt[j] == bd) ? 1 : 0;
+        const int os = wave_incl_sum(cs) - cs, ot = wave_incl_sum(ct) - ct;
+        const int ns = __shfl(os + cs, 63, 64), nt = __shfl(ot + ct, 63, 64);
+        {
+          int w = os;
+          for (int i = lane; i < nd; i += 64)
+            if (!L.vs[i] && L.ds[i] == bd) {
+              bs[w++] = (uint16_t)i;
+              L.vs[i] = 1;
+            }
+          w = ot;
+          for (int j = lane; j < nq; j += 64)
+            if (!L.vt[j] && L.dt[j] == bd) {
+              bt[w++] = (uint16_t)j;
+              L.vt[j] = 1;
+            }
+        }
+        __syncthreads();
+        // forward edges from the level's doc items
+        for (int j = lane; j < nq; j += 64) {
+          if (L.vt[j]) continue;
+          double best = L.dt[j];
+          int pred = L.prt[j];
           const double pj = L.pt[j];
-          for (int i = lane; i < nd; i += 64) {
-            if (!L.vs[i] && Fj[i] > 0u) {
-              const double rc = -((double)S[(int64_t)i * nq + j] + L.ps[i] - pj);
-              const double nd2 = bd + (rc > 0.0 ? rc : 0.0);
-              if (nd2 < L.ds[i]) {
-                L.ds[i] = nd2;
-                L.prs[i] = (uint16_t)j;
-              }
+          for (int b = 0; b < ns; ++b) {
+            const int i = bs[b];
+            const double rc = (double)S[(int64_t)i * nq + j] + L.ps[i] - pj;
+            const double nd2 = bd + (rc > 0.0 ? rc : 0.0);
+            if (nd2 < best) {
+              best = nd2;
+              pred = i;
             }
           }
-        } else {
-          const int i = (int)(bk & 0xFFFFu);
-          if (lane == 0) L.vs[i] = 1;
-          const float* Di = S + (int64_t)i * nq;
+          L.dt[j] = best;
+          L.prt[j] = (uint16_t)pred;
+        }
+        // backward edges from the level's query items, where a flow is positive
+        for (int i = lane; i < nd; i += 64) {
+          if (L.vs[i]) continue;
+          double best = L.ds[i];
+          int pred = L.prs[i];
           const double pi = L.ps[i];
-          for (int j = lane; j < nq; j += 64) {
-            if (!L.vt[j]) {
-              const double rc = (double)Di[j] + pi - L.pt[j];
+          for (int b = 0; b < nt; ++b) {
+            const int j = bt[b];
+            if (F[(int64_t)j * nd + i] > 0u) {
+              const double rc = -((double)S[(int64_t)i * nq + j] + pi - L.pt[j]);
               const double nd2 = bd + (rc > 0.0 ? rc : 0.0);
-              if (nd2 < L.dt[j]) {
-                L.dt[j] = nd2;
-                L.prt[j] = (uint16_t)i;
+              if (nd2 < best) {
+                best = nd2;
+                pred = j;
               }
             }
           }
+          L.ds[i] = best;
+          L.prs[i] = (uint16_t)pred;
         }
         __syncthreads();
       }
