@@ -10,6 +10,8 @@ Contents, each following the paper:
 * ``Tree``: the randomly shifted quadtree (Section 2), built by literal
   recursive halving in ``oracle.c``; Morton rank = depth-first leaf order.
 * ``Tree.quadtree``: closed form sum_v w(v) |mu(v) - nu(v)| (Section 2).
+* ``Tree.quadtree_eps``: the same with edge weights (2^level)^(1 - eps), the
+  tree of the proof of the uniform-distribution Flowtree upper bound.
 * ``Tree.flowtree``: bottom-up greedy tree flow (Appendix A.1) priced with
   Euclidean distances (Section 3), float64.
 * ``exact_w1_*``: W1 of Section 1, eq. (1), three independent ways (LP,
@@ -84,6 +86,8 @@ def load(path: str):
     lib.oracle_lca_depth.restype = i32
     lib.oracle_quadtree.argtypes = [p, p, p, i64, p, p, i64, i32, p]
     lib.oracle_quadtree.restype = ctypes.c_int
+    lib.oracle_quadtree_eps.argtypes = [p, p, p, i64, p, p, i64, i32, ctypes.c_double, p]
+    lib.oracle_quadtree_eps.restype = ctypes.c_int
     lib.oracle_flowtree.argtypes = [p, p, p, p, i64, p, p, i64, i32, p, p, p, p, p, p]
     lib.oracle_flowtree.restype = ctypes.c_int
     lib.oracle_exact_w1_ssp.argtypes = [p, i32, p, p, i64, p, p, i64, i32, p]
@@ -174,6 +178,19 @@ class Tree:
         if rc != OR_OK:
             raise OracleError("quadtree: invalid input (%d)" % rc)
         return int(out[0])
+
+    def quadtree_eps(self, mu_id, mu_m, nu_id, nu_m, Q: int, eps: float) -> float:
+        """Quadtree with eps-weighted edges: sum over non-root cells v of
+        (2^(B-depth v))^(1-eps) |mu(v) - nu(v)|, masses as fractions, float64
+        (the weights of the proof of the uniform-distribution Flowtree bound;
+        eps = 0 is the plain Quadtree / 2^Q)."""
+        mu_id, mu_m, nu_id, nu_m = _u32(mu_id), _u32(mu_m), _u32(nu_id), _u32(nu_m)
+        out = ctypes.c_double(0.0)
+        rc = self._L.oracle_quadtree_eps(self._h, _p(mu_id), _p(mu_m), len(mu_id), _p(nu_id),
+                                        _p(nu_m), len(nu_id), Q, ctypes.c_double(eps), ctypes.byref(out))
+        if rc != OR_OK:
+            raise OracleError("quadtree_eps: invalid input (%d)" % rc)
+        return out.value
 
     def quadtree_value(self, *a, Q: int) -> float:
         """Quadtree estimate in the units of X (float64)."""

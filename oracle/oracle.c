@@ -403,6 +403,45 @@ typedef struct {
   int64_t next;        /* inbox linked list */
 } item_t;
 
+/* Quadtree with the edge above a depth-k cell weighted (2^(B-k))^(1-eps)
+ * (the eps-weighted tree of the proof of the uniform-distribution upper
+ * bound for Flowtree): sum over non-root cells of the weight times
+ * |mu(v) - nu(v)|, masses as fractions of 2^Q, float64. */
+int oracle_quadtree_eps(otree* t, const uint32_t* mu_id, const uint32_t* mu_m, int64_t n_mu,
+                        const uint32_t* nu_id, const uint32_t* nu_m, int64_t n_nu,
+                        int32_t Q, double eps, double* out) {
+  if (check_dist(t, mu_id, mu_m, n_mu, Q) || check_dist(t, nu_id, nu_m, n_nu, Q))
+    return OR_EINVAL;
+  t->stamp_id++;
+  int64_t cap = (n_mu + n_nu) * (t->B + 1) + 1, nt = 0;
+  int64_t* touched = (int64_t*)malloc(cap * sizeof(int64_t));
+  if (!touched) return OR_ENOMEM;
+  for (int side = 0; side < 2; ++side) {
+    const uint32_t* id = side ? nu_id : mu_id;
+    const uint32_t* m = side ? nu_m : mu_m;
+    int64_t n = side ? n_nu : n_mu;
+    for (int64_t a = 0; a < n; ++a) {
+      for (int64_t v = t->leaf_of[id[a]]; v != 0; v = t->parent[v]) {
+        if (t->stamp[v] != t->stamp_id) {
+          t->stamp[v] = t->stamp_id;
+          t->acc[v] = 0;
+          touched[nt++] = v;
+        }
+        t->acc[v] += side ? -(int64_t)m[a] : (int64_t)m[a];
+      }
+    }
+  }
+  double s = 0.0;
+  for (int64_t i = 0; i < nt; ++i) {
+    int64_t v = touched[i];
+    int64_t a = t->acc[v] < 0 ? -t->acc[v] : t->acc[v];
+    s += (double)a * pow(2.0, (double)(t->B - t->depth[v]) * (1.0 - eps));
+  }
+  free(touched);
+  *out = ldexp(s, -Q);
+  return OR_OK;
+}
+
 static int cmp_rank(const void* a, const void* b) {
   const item_t* x = *(item_t* const*)a;
   const item_t* y = *(item_t* const*)b;
