@@ -189,7 +189,32 @@ ft_status ft_flowtree_flows(ft_index* index, const int64_t* q_off, const uint32_
                             int32_t* count, uint32_t* flow_d, uint32_t* flow_q,
                             uint32_t* flow_eta, uint8_t* flow_bind, void* stream);
 
-/* Quadtree keys (as ft_quadtree_knn) of explicit pairs: out_key[n_pairs]. */
+/* ------------------------------------------------------------------------
+ * ft_quadtree_eps_pairs / ft_quadtree_eps_knn -- the Quadtree estimate on
+ * the tree with eps-weighted edges used in the proof of the
+ * uniform-distribution Flowtree upper bound: the edge above a cell of side
+ * 2^l grid units weighs 2^(l (1 - eps)); eps = 0 is ft_quadtree_knn's key /
+ * 2^Q.  Values sum_v w(v) |mu(v) - nu(v)| in units of mass fraction x grid
+ * unit^(1 - eps), fp64 with integer masses.
+ * eps         in [0, 1].
+ * _pairs: out[n_pairs] device float64 for pairs (pair_q[p], pair_d[p]).
+ * _knn:   candidate lists only (cand[n_q * n_cand], n_cand <= 4096);
+ *         out_cost[n_q*k] float32 and out_doc ordered by (value, doc index).
+ * A query may touch at most 4096 tree cells (FT_ERANGE).
+ * (The Flowtree flow does not depend on the edge weights: the greedy is
+ * optimal for any positive weights, so Flowtree has no eps variant.)
+ * ---------------------------------------------------------------------- */
+ft_status ft_quadtree_eps_pairs(ft_index* index, const int64_t* q_off, const uint32_t* q_id,
+                                const uint32_t* q_mass, int64_t n_q, const int64_t* pair_q,
+                                const int64_t* pair_d, int64_t n_pairs, double eps, double* out,
+                                void* stream);
+ft_status ft_quadtree_eps_knn(ft_index* index, const int64_t* q_off, const uint32_t* q_id,
+                              const uint32_t* q_mass, int64_t n_q, const int64_t* cand,
+                              int32_t n_cand, double eps, int32_t k, float* out_cost,
+                              int64_t* out_doc, void* stream);
+
+/* Quadtree keys (as ft_quadtree_knn) of explicit pairs: out_key[n_pairs].
+ * A query may touch at most 4096 tree cells (FT_ERANGE). */
 ft_status ft_quadtree_pairs(ft_index* index, const int64_t* q_off, const uint32_t* q_id,
                             const uint32_t* q_mass, int64_t n_q, const int64_t* pair_q,
                             const int64_t* pair_d, int64_t n_pairs, uint64_t* out_key,

@@ -59,6 +59,8 @@ def load():
         "ft_act_knn": ([p, p, p, p, i64, p, i32, i32, i32, p, p, p], ctypes.c_int),
         "ft_act_pairs": ([p, p, p, p, i64, p, p, i64, i32, p, p], ctypes.c_int),
         "ft_last_rerank_stats": ([p, p], ctypes.c_int),
+        "ft_quadtree_eps_pairs": ([p, p, p, p, i64, p, p, i64, ctypes.c_double, p, p], ctypes.c_int),
+        "ft_quadtree_eps_knn": ([p, p, p, p, i64, p, i32, ctypes.c_double, i32, p, p, p], ctypes.c_int),
         "ft_exact_knn": ([p, p, p, p, i64, p, i32, i32, p, p, p], ctypes.c_int),
         "ft_exact_pairs": ([p, p, p, p, i64, p, p, i64, p, p], ctypes.c_int),
         "ft_sinkhorn_knn": ([p, p, p, p, i64, p, i32, i32, ctypes.c_float, i32, p, p, p], ctypes.c_int),
@@ -279,6 +281,30 @@ def exact_pairs(index: Index, q_off, q_id, q_mass, pair_q, pair_d):
                                  q_off.numel() - 1, _ptr(pair_q), _ptr(pair_d), pair_q.numel(), _ptr(out),
                                  _stream()))
     return out
+
+
+def quadtree_eps_pairs(index: Index, q_off, q_id, q_mass, pair_q, pair_d, eps: float):
+    """ft_quadtree_eps_pairs -> float64 eps-weighted Quadtree value per pair."""
+    q_off, q_id, q_mass = _queries(q_off, q_id, q_mass)
+    pair_q, pair_d = _i64(pair_q), _i64(pair_d)
+    out = torch.empty(pair_q.numel(), dtype=torch.float64, device=q_off.device)
+    _check(load().ft_quadtree_eps_pairs(index.handle, _ptr(q_off), _ptr(q_id), _ptr(q_mass),
+                                        q_off.numel() - 1, _ptr(pair_q), _ptr(pair_d), pair_q.numel(), eps,
+                                        _ptr(out), _stream()))
+    return out
+
+
+def quadtree_eps_knn(index: Index, q_off, q_id, q_mass, k: int, cand, eps: float):
+    """ft_quadtree_eps_knn -> (values float32 [n_q, k], docs int64 [n_q, k])."""
+    q_off, q_id, q_mass = _queries(q_off, q_id, q_mass)
+    n_q = q_off.numel() - 1
+    cand_t = _i64(cand)
+    costs = torch.empty((n_q, k), dtype=torch.float32, device=q_off.device)
+    docs = torch.empty((n_q, k), dtype=torch.int64, device=q_off.device)
+    _check(load().ft_quadtree_eps_knn(index.handle, _ptr(q_off), _ptr(q_id), _ptr(q_mass), n_q,
+                                      _ptr(cand_t), cand_t.shape[-1], eps, k, _ptr(costs), _ptr(docs),
+                                      _stream()))
+    return costs, docs
 
 
 def quadtree_pairs(index: Index, q_off, q_id, q_mass, pair_q, pair_d):

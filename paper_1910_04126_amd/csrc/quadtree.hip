@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <type_traits>
 #include <vector>
 
@@ -400,6 +401,54 @@ __global__ __launch_bounds__(64) void k_qt_pairs(const int64_t* __restrict__ pai
   if (threadIdx.x == 0) out[p] = q_S[q] + d_S[doc] - 2 * acc;
 }
 
+// The eps-weighted Quadtree (the tree of the proof of the uniform-distribution
+// Flowtree upper bound: the edge above a depth-k cell weighs w[k] =
+// (2^(B-k))^(1-eps)) of (query, doc) pairs, as
+// sum_v w (a_v + b_v - 2 min(a_v, b_v)) over the cells of either side, in
+// fp64 with integer masses; one wavefront per pair, the query table in LDS.
+// Pairs: explicit (pair_q, pair_d), or query p / n_cols against
+// cand[p].  Output: out_d (fp64) or out_f (fp32), in units of mass fraction
+// x grid unit^(1-eps).
+__global__ __launch_bounds__(64) void k_qt_eps(const int64_t* __restrict__ pair_q, const int64_t* __restrict__ pair_d,
+                                               const int64_t* __restrict__ cand, int64_t n_cols, int64_t n_pairs,
+                                               const int64_t* __restrict__ q_eoff, const uint32_t* __restrict__ q_ekey,
+                                               const uint32_t* __restrict__ q_emass,
+                                               const int64_t* __restrict__ d_eoff, const uint32_t* __restrict__ d_ekey,
+                                               const uint32_t* __restrict__ d_emass, const double* __restrict__ w,
+                                               int Q, double* __restrict__ out_d, float* __restrict__ out_f) {
+  __shared__ uint32_t tk[8192];
+  __shared__ uint32_t tm[8192];
+  const int64_t p = blockIdx.x;
+  if (p >= n_pairs) return;
+  int64_t q, doc;
+  if (pair_q) {
+    q = pair_q[p];
+    doc = pair_d[p];
+  } else {
+    q = p / n_cols;
+    doc = cand[p];
+  }
+  const int64_t nq = q_eoff[q + 1] - q_eoff[q];
+  int lg = 1;
+  while ((1ll << lg) < 2 * nq) ++lg;
+  QtTile tile{(int32_t)q, 1, lg, 0};
+  qt_build_tables<8192>(tk, tm, tile, q_eoff, q_ekey, q_emass);
+  double acc = 0.0;
+  for (int64_t e = d_eoff[doc] + threadIdx.x; e < d_eoff[doc + 1]; e += 64) {
+    const uint32_t key = d_ekey[e];
+    const uint32_t a = d_emass[e], b = qt_lookup(tk, tm, lg, key);
+    acc += w[key >> KEY_DEPTH_SHIFT] * ((double)a - 2.0 * (double)(a < b ? a : b));
+  }
+  for (int64_t e = q_eoff[q] + threadIdx.x; e < q_eoff[q + 1]; e += 64)
+    acc += w[q_ekey[e] >> KEY_DEPTH_SHIFT] * (double)q_emass[e];
+  acc = wave_sum(acc);
+  if (threadIdx.x == 0) {
+    const double v = ldexp(acc, -Q);
+    if (out_d) out_d[p] = v;
+    else out_f[p] = (float)v;
+  }
+}
+
 __global__ void k_check_index(const int64_t* __restrict__ v, int64_t n, int64_t bound, uint32_t* __restrict__ status) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n && (v[i] < 0 || v[i] >= bound)) atomicOr(status, ERR_ID_RANGE);
@@ -413,6 +462,17 @@ void check_indices(ft_index* ix, const int64_t* v, int64_t n, int64_t bound, hip
 }
 
 constexpr int SLOTS_SMALL = 4096, SLOTS_LARGE = 8192;
+
+// The query hash tables in LDS hold at most SLOTS_LARGE / 2 cells of one
+// query (load factor 1/2): FT_ERANGE for a query that touches more.
+static void require_query_cells(ft_index* ix, int64_t n_q, hipStream_t s) {
+  std::vector<int64_t> eoff(n_q + 1);
+  FT_HIP(hipMemcpyAsync(eoff.data(), ix->qry.ecnt.p, (n_q + 1) * 8, hipMemcpyDeviceToHost, s));
+  FT_HIP(hipStreamSynchronize(s));
+  for (int64_t q = 0; q < n_q; ++q)
+    FT_REQUIRE(eoff[q + 1] - eoff[q] <= SLOTS_LARGE / 2, FT_ERANGE,
+               "a query may touch at most 4096 tree cells here");
+}
 
 // Inverted doc lists for ranking all docs, made once per index.
 static void prepare_postings(ft_index* ix, hipStream_t s) {
@@ -577,11 +637,78 @@ extern "C" ft_status ft_quadtree_pairs(ft_index* ix, const int64_t* q_off, const
     check_indices(ix, pair_q, n_pairs, n_q, s, "pair_q");
     check_indices(ix, pair_d, n_pairs, ix->docs.n, s, "pair_d");
     if (n_pairs == 0) return;
+    require_query_cells(ix, n_q, s);
     k_qt_pairs<<<(unsigned)n_pairs, 64, 0, s>>>(pair_q, pair_d, n_pairs, ix->qry.ecnt.as<int64_t>(),
                                                ix->qry.ekey.as<uint32_t>(), ix->qry.emass.as<uint32_t>(),
                                                ix->qry.S.as<uint64_t>(), ix->docs.ecnt.as<int64_t>(),
                                                ix->docs.ekey.as<uint32_t>(), ix->docs.emass.as<uint32_t>(),
                                                ix->docs.S.as<uint64_t>(), ix->B, out_key);
     FT_HIP(hipGetLastError());
+  });
+}
+
+// Edge weights (2^(B-k))^(1-eps) for depths k = 0..B, on the device.
+static const double* eps_weights(ft_index* ix, double eps, hipStream_t s) {
+  std::vector<double> w(ix->B + 1);
+  for (int k = 0; k <= ix->B; ++k) w[k] = std::pow(2.0, (double)(ix->B - k) * (1.0 - eps));
+  double* d = (double*)ix->ws_misc.ensure(w.size() * sizeof(double));
+  FT_HIP(hipMemcpyAsync(d, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  FT_HIP(hipStreamSynchronize(s));
+  return d;
+}
+
+extern "C" ft_status ft_quadtree_eps_pairs(ft_index* ix, const int64_t* q_off, const uint32_t* q_id,
+                                           const uint32_t* q_mass, int64_t n_q, const int64_t* pair_q,
+                                           const int64_t* pair_d, int64_t n_pairs, double eps, double* out,
+                                           void* stream) {
+  return guarded([&] {
+    FT_REQUIRE(ix && pair_q && pair_d && out, FT_EINVAL, "NULL argument");
+    FT_REQUIRE(n_pairs >= 0, FT_EINVAL, "n_pairs < 0");
+    FT_REQUIRE(eps >= 0.0 && eps <= 1.0, FT_EINVAL, "eps must lie in [0, 1]");
+    std::lock_guard<std::mutex> lock(ix->mu);
+    hipStream_t s = (hipStream_t)stream;
+    prepare_dists(ix, ix->qry, q_off, q_id, q_mass, n_q, true, s, "queries");
+    check_indices(ix, pair_q, n_pairs, n_q, s, "pair_q");
+    check_indices(ix, pair_d, n_pairs, ix->docs.n, s, "pair_d");
+    if (n_pairs == 0) return;
+    require_query_cells(ix, n_q, s);
+    const double* w = eps_weights(ix, eps, s);
+    k_qt_eps<<<(unsigned)n_pairs, 64, 0, s>>>(pair_q, pair_d, nullptr, 1, n_pairs, ix->qry.ecnt.as<int64_t>(),
+                                             ix->qry.ekey.as<uint32_t>(), ix->qry.emass.as<uint32_t>(),
+                                             ix->docs.ecnt.as<int64_t>(), ix->docs.ekey.as<uint32_t>(),
+                                             ix->docs.emass.as<uint32_t>(), w, ix->Q, out, nullptr);
+    FT_HIP(hipGetLastError());
+    FT_HIP(hipStreamSynchronize(s));
+  });
+}
+
+extern "C" ft_status ft_quadtree_eps_knn(ft_index* ix, const int64_t* q_off, const uint32_t* q_id,
+                                         const uint32_t* q_mass, int64_t n_q, const int64_t* cand, int32_t n_cand,
+                                         double eps, int32_t k, float* out_cost, int64_t* out_doc, void* stream) {
+  return guarded([&] {
+    FT_REQUIRE(ix && cand && out_cost && out_doc, FT_EINVAL, "NULL argument");
+    FT_REQUIRE(eps >= 0.0 && eps <= 1.0, FT_EINVAL, "eps must lie in [0, 1]");
+    FT_REQUIRE(n_cand >= 1 && n_cand <= 4096, FT_ERANGE, "n_cand must lie in [1, 4096]");
+    FT_REQUIRE(k >= 1 && k <= n_cand, FT_EINVAL, "k must lie in [1, n_cand]");
+    std::lock_guard<std::mutex> lock(ix->mu);
+    hipStream_t s = (hipStream_t)stream;
+    prepare_dists(ix, ix->qry, q_off, q_id, q_mass, n_q, true, s, "queries");
+    check_indices(ix, cand, n_q * n_cand, ix->docs.n, s, "cand");
+    require_query_cells(ix, n_q, s);
+    const double* w = eps_weights(ix, eps, s);
+    const int64_t rows = std::max<int64_t>(1, std::min<int64_t>(n_q, (int64_t(1) << 28) / n_cand));
+    float* cost = (float*)ix->ws_cost.ensure(rows * n_cand * 4);
+    for (int64_t r0 = 0; r0 < n_q; r0 += rows) {
+      const int64_t r1 = std::min(n_q, r0 + rows);
+      const int64_t np = (r1 - r0) * n_cand;
+      k_qt_eps<<<(unsigned)np, 64, 0, s>>>(nullptr, nullptr, cand + r0 * n_cand, n_cand, np,
+                                          ix->qry.ecnt.as<int64_t>() + r0, ix->qry.ekey.as<uint32_t>(),
+                                          ix->qry.emass.as<uint32_t>(), ix->docs.ecnt.as<int64_t>(),
+                                          ix->docs.ekey.as<uint32_t>(), ix->docs.emass.as<uint32_t>(), w, ix->Q,
+                                          nullptr, cost);
+      FT_HIP(hipGetLastError());
+      topk_rows(cost, r1 - r0, n_cand, cand + r0 * n_cand, k, out_cost + r0 * k, out_doc + r0 * k, s);
+    }
+    FT_HIP(hipStreamSynchronize(s));
   });
 }
