@@ -20,6 +20,12 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload batched|t
        python bench.py --workload random_model [--reps R]   (the Section 3.2 experiment: success
                                                               rate of recovering the planted nearest
                                                               neighbour, Quadtree vs Flowtree, vs N)
+       python bench.py --workload recall [--trees T]   (recall@m of Quadtree, eps-weighted Quadtree
+                                                 and Flowtree against the exact W1 nearest neighbour, mean
+                                                 and std over T random shifts; R-WMD, ACT-1 and
+                                                 Sinkhorn-1 beside them)
+       python bench.py --workload grad   (forward + backward of the Flowtree cost of 256 pairs on
+                                          V = 50k points in R^300, tree and flow pattern frozen)
        python bench.py --calibrate-copy BYTES   (a plain device copy of BYTES, five times: the
                                                  reference for the HBM byte counters)
 """
@@ -94,11 +100,16 @@ def main():
     ap.add_argument("--act-cand", type=int, default=0)
     ap.add_argument("--act-iters", type=int, default=1)
     ap.add_argument("--sk-iters", type=int, default=1)
+    ap.add_argument("--trees", type=int, default=5)
     args = ap.parse_args()
     if args.calibrate_copy:
         return calibrate_copy(args.calibrate_copy)
     if args.workload == "random_model":
         return random_model_experiment(args)
+    if args.workload == "recall":
+        return recall_experiment(args)
+    if args.workload == "grad":
+        return grad_bench(args)
     if args.workload in ("act", "sinkhorn", "exact"):
         return rerank_stage(args, args.workload)
     if args.gpus != 1:
@@ -317,6 +328,217 @@ def random_model_experiment(args):
            "results": results,
            "gpu_seconds": round(gpu_s, 2), "wall_seconds": round(time.time() - t_all, 2),
            "pairs_per_s_incl_index_build": round(pairs / gpu_s, 1)}
+    print(json.dumps(out), flush=True)
+
+
+def grad_bench(args):
+    """Differentiation workload: V = 50k points in R^300 (text law), 256
+    (query, doc) pairs with supports 20..200.  One step = the forward pass
+    (Flowtree cost of every pair; saves the flows) and the backward pass
+    (gradients of sum_p g_p cost_p w.r.t. X and both weight vectors, tree and
+    flow pattern frozen), gradient buffers cleared in the step.  value =
+    pairs / step time.  roofline: algorithmic bytes (items and coordinate
+    rows read by each pass, plus one fp32 gradient row per item written) over
+    the device time of the two passes."""
+    if args.gpus != 1:
+        print("bench.py measures one GPU only", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import gen
+    import paper_1910_04126_amd as ft
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    def T(a):
+        a = np.ascontiguousarray(a)
+        if a.dtype == np.uint32:
+            a = a.view(np.int32)
+        return torch.from_numpy(a).to(dev)
+
+    ds = gen.make("grad")
+    ix = ft.build_tree(T(ds.X), ds.shift, ds.B, T(ds.doc_off), T(ds.doc_id), T(ds.doc_mass), ds.Q)
+    X = T(ds.X)
+    q = (T(ds.q_off), T(ds.q_id), T(ds.q_mass))
+    pq, pd = T(ds.extra["pair_q"]), T(ds.extra["pair_d"])
+    n_p = len(ds.extra["pair_q"])
+    cost = torch.empty(n_p, dtype=torch.float32, device=dev)
+    g = torch.linspace(0.5, 1.5, n_p, dtype=torch.float32, device=dev)
+    gX = torch.zeros_like(X)
+    gq = torch.zeros(len(ds.q_id), dtype=torch.float32, device=dev)
+    gd = torch.zeros(len(ds.doc_id), dtype=torch.float32, device=dev)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+
+    def step():
+        ev[0].record()
+        ft.flowtree_cost_grad(ix, X, *q, pq, pd, ft.FT_FWD, cost=cost)
+        ev[1].record()
+        gX.zero_()
+        gq.zero_()
+        gd.zero_()
+        ft.flowtree_cost_grad(ix, X, *q, pq, pd, ft.FT_BWD, grad_out=g, grad_X=gX, grad_qmass=gq, grad_dmass=gd)
+        ev[2].record()
+
+    for _ in range(max(1, args.warmup)):
+        step()
+    torch.cuda.synchronize()
+    fwd, bwd = [], []
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+        torch.cuda.synchronize()
+        fwd.append(ev[0].elapsed_time(ev[1]))
+        bwd.append(ev[1].elapsed_time(ev[2]))
+    elapsed = time.perf_counter() - t_start
+    ms_step = 1000.0 * elapsed / args.steps
+    sq = np.diff(ds.q_off)[ds.extra["pair_q"]]
+    sdd = np.diff(ds.doc_off)[ds.extra["pair_d"]]
+    items = float((sq + sdd).sum())
+    row = 4.0 * ds.d
+    alg = 2.0 * items * (8.0 + row) + items * row
+    dev_ms = float(np.mean(fwd) + np.mean(bwd))
+    achieved = alg / (dev_ms * 1e-3) / 1e9
+    log("grad: forward %.3f ms, backward %.3f ms (events), step %.3f ms" % (np.mean(fwd), np.mean(bwd), ms_step))
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        Tr = oracle.Tree(ds.X, ds.shift, ds.B)
+        done = 0
+        t0 = time.perf_counter()
+        for p in range(n_p):
+            qq, dd = ds.extra["pair_q"][p], ds.extra["pair_d"][p]
+            a, b = ds.doc_off[dd], ds.doc_off[dd + 1]
+            qa, qb = ds.q_off[qq], ds.q_off[qq + 1]
+            _, fl = Tr.flowtree(ds.doc_id[a:b], ds.doc_mass[a:b], ds.q_id[qa:qb], ds.q_mass[qa:qb], Q=ds.Q)
+            oracle.frozen_grad(ds.X, ds.doc_id[a:b], ds.q_id[qa:qb], fl, ds.doc_mass[a:b] / 2.0 ** ds.Q,
+                               ds.q_mass[qa:qb] / 2.0 ** ds.Q)
+            done += 1
+            if time.perf_counter() - t0 > 15.0:
+                break
+        el = time.perf_counter() - t0
+        cpu = {"value": round(done / el, 2), "unit": "pairs/s", "cores": 1, "kind": "oracle",
+               "sample": "%d of %d pairs: oracle Flowtree (C) then the float64 frozen cost gradient (numpy), "
+                         "single-threaded" % (done, n_p)}
+    out = {"metric": "Flowtree cost forward + backward (query, doc) pairs/sec on 1 MI355X",
+           "value": round(n_p / (elapsed / args.steps), 1), "unit": "pairs/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "differentiation: V=50000 points in R^300 (L2-normalised 200-cluster mixture), "
+                                  "256 (query, doc) pairs with supports 20..200; gradient of sum_p g_p cost_p "
+                                  "w.r.t. X and both weight vectors, tree and flow frozen",
+                      "pairs": n_p, "V": ds.V, "d": ds.d},
+           "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                        "kernel": "k_flow_save + k_flow_bwd (forward and backward passes)",
+                        "kernel_ms": round(dev_ms, 4), "algorithmic_bytes": alg},
+           "stages": {"forward_ms": round(float(np.mean(fwd)), 4), "backward_ms": round(float(np.mean(bwd)), 4)},
+           "cpu_baseline": cpu}
+    print(json.dumps(out), flush=True)
+
+
+RECALL_AT = (1, 2, 4, 8, 16, 32, 64, 128)
+
+
+def recall_experiment(args):
+    """Accuracy of the estimates as nearest-neighbour rankers (Section 4.2:
+    recall@m = the fraction of queries whose true nearest neighbour, by exact
+    W1, is among the top m candidates of a method; the randomised tree methods
+    reported as mean and standard deviation over independent random shifts,
+    five in the paper).  Three synthetic worlds stand in for the paper's
+    datasets: the tiny-config law (R^16 mixture, 10..30 points), the text law
+    (R^300, 20..200 words) and stroke images on the 28x28 grid.  Every value
+    comes from the GPU path: exact W1 over all docs gives the truth; Quadtree,
+    the eps-weighted Quadtree (eps = 1 / log2 of the mean support, the
+    weighting of the uniform-distribution Flowtree bound) and Flowtree rank all
+    docs under each shift; R-WMD, ACT-1 and Sinkhorn-1 (deterministic) once."""
+    if args.gpus != 1:
+        print("bench.py measures one GPU only", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import gen
+    import paper_1910_04126_amd as ft
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    def T(a):
+        a = np.ascontiguousarray(a)
+        if a.dtype == np.uint32:
+            a = a.view(np.int32)
+        return torch.from_numpy(a).to(dev)
+
+    worlds = [
+        ("tiny configuration: V=2000 in R^16, 20-cluster mixture; 500 docs, 10 queries of 10..30 points",
+         gen.make("tiny")),
+        ("tiny law: V=2000 in R^16, 20-cluster mixture; 1000 docs, 200 queries of 10..30 points",
+         gen.make("tiny", n_docs=1000, n_queries=200)),
+        ("text law: V=20000 in R^300, L2-normalised 200-cluster mixture; 1000 docs, 50 queries of 20..200 words",
+         gen.make("text", V=20000, n_docs=1000, n_queries=50)),
+        ("image law: 28x28 grid; 1000 stroke images, 50 queries of 100..200 pixels (Q=16)",
+         gen.make("image", n_docs=1000, n_queries=50)),
+    ]
+    M = max(RECALL_AT)
+    t_all = time.time()
+    results = []
+    for desc, ds in worlds:
+        n_q, n_d = ds.n_queries, ds.n_docs
+        docs = (T(ds.doc_off), T(ds.doc_id), T(ds.doc_mass))
+        q = (T(ds.q_off), T(ds.q_id), T(ds.q_mass))
+        Xd = T(ds.X)
+        ix = ft.build_tree(Xd, ds.shift, ds.B, *docs, ds.Q)
+        t0 = time.perf_counter()
+        _, truth = ft.exact_knn(ix, *q, 1)
+        torch.cuda.synchronize()
+        exact_s = time.perf_counter() - t0
+        truth = truth.cpu().numpy()[:, 0]
+        log("%s: exact W1 of %d pairs in %.1fs" % (desc, n_q * n_d, exact_s))
+
+        def recall(ranked):
+            ranked = np.asarray(ranked)
+            hit = ranked == truth[:, None]
+            first = np.where(hit.any(axis=1), hit.argmax(axis=1), M)
+            return [round(float(np.mean(first < m)), 4) for m in RECALL_AT]
+
+        mean_s = float(np.mean(np.diff(ds.q_off)))
+        eps = 1.0 / np.log2(mean_s)
+        cand_all = T(np.tile(np.arange(n_d, dtype=np.int64), (n_q, 1)))
+        per = {"quadtree": [], "quadtree_eps": [], "flowtree": []}
+        rng = np.random.default_rng(1234)
+        for tree in range(args.trees):
+            shift = gen.random_shift(rng, ds.d, ds.B)
+            tix = ft.build_tree(Xd, shift, ds.B, *docs, ds.Q)
+            _, qd = ft.quadtree_knn(tix, *q, M)
+            _, qe = ft.quadtree_eps_knn(tix, *q, M, cand_all, eps)
+            _, fd = ft.flowtree_knn(tix, *q, M, mode=ft.FT_BATCHED)
+            per["quadtree"].append(recall(qd.cpu().numpy()))
+            per["quadtree_eps"].append(recall(qe.cpu().numpy()))
+            per["flowtree"].append(recall(fd.cpu().numpy()))
+            del tix
+        row = {"world": desc, "docs": n_d, "queries": n_q, "trees": args.trees, "eps": round(eps, 4),
+               "recall_at": list(RECALL_AT), "exact_w1_seconds": round(exact_s, 2)}
+        for name, v in per.items():
+            v = np.asarray(v)
+            row[name] = {"mean": [round(float(x), 4) for x in v.mean(axis=0)],
+                         "std": [round(float(x), 4) for x in v.std(axis=0)]}
+        for name, f in (("rwmd", lambda: ft.act_knn(ix, *q, M, iters=0)),
+                        ("act1", lambda: ft.act_knn(ix, *q, M, iters=1)),
+                        ("sinkhorn1", lambda: ft.sinkhorn_knn(ix, *q, M, iters=1))):
+            _, dd = f()
+            row[name] = recall(dd.cpu().numpy())
+        log("  recall@%s" % (list(RECALL_AT),))
+        for name in ("quadtree", "quadtree_eps", "flowtree"):
+            log("  %-13s %s +- %s" % (name, row[name]["mean"], row[name]["std"]))
+        for name in ("rwmd", "act1", "sinkhorn1"):
+            log("  %-13s %s" % (name, row[name]))
+        results.append(row)
+        del ix
+    out = {"metric": "recall@m of the true (exact W1) nearest neighbour, per method",
+           "unit": "fraction", "higher_is_better": True, "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": "accuracy experiment of Section 4.2 on synthetic stand-ins; tree methods over "
+                                  "%d random shifts" % args.trees},
+           "results": results, "wall_seconds": round(time.time() - t_all, 2)}
     print(json.dumps(out), flush=True)
 
 
