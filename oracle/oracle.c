@@ -353,19 +353,16 @@ static int check_dist(otree* t, const uint32_t* id, const uint32_t* m,
 
 /* -------------------------------------------------------------- quadtree -- */
 
-/* Quadtree estimate in integer units of 2^-Q mass x grid unit:
- * U = sum over non-root nodes v of 2^(B - depth v) * |mu(v) - nu(v)|,
- * with mu(v) the mass of mu's points inside v (Section 2, closed form).
- * Returns 0 and writes *out, or a negative status. */
-int oracle_quadtree(otree* t, const uint32_t* mu_id, const uint32_t* mu_m, int64_t n_mu,
-                    const uint32_t* nu_id, const uint32_t* nu_m, int64_t n_nu,
-                    int32_t Q, uint64_t* out) {
-  if (check_dist(t, mu_id, mu_m, n_mu, Q) || check_dist(t, nu_id, nu_m, n_nu, Q))
-    return OR_EINVAL;
+/* mu(v) - nu(v) for every non-root cell v that either distribution touches,
+ * left in t->acc[v]; returns the list of those cells (caller frees) and its
+ * length in *nt, or NULL when out of memory. */
+static int64_t* cell_mass_differences(otree* t, const uint32_t* mu_id, const uint32_t* mu_m, int64_t n_mu,
+                                      const uint32_t* nu_id, const uint32_t* nu_m, int64_t n_nu,
+                                      int64_t* nt_out) {
   t->stamp_id++;
   int64_t cap = (n_mu + n_nu) * (t->B + 1) + 1, nt = 0;
   int64_t* touched = (int64_t*)malloc(cap * sizeof(int64_t));
-  if (!touched) return OR_ENOMEM;
+  if (!touched) return NULL;
   for (int side = 0; side < 2; ++side) {
     const uint32_t* id = side ? nu_id : mu_id;
     const uint32_t* m = side ? nu_m : mu_m;
@@ -381,6 +378,22 @@ int oracle_quadtree(otree* t, const uint32_t* mu_id, const uint32_t* mu_m, int64
       }
     }
   }
+  *nt_out = nt;
+  return touched;
+}
+
+/* Quadtree estimate in integer units of 2^-Q mass x grid unit:
+ * U = sum over non-root nodes v of 2^(B - depth v) * |mu(v) - nu(v)|,
+ * with mu(v) the mass of mu's points inside v (Section 2, closed form).
+ * Returns 0 and writes *out, or a negative status. */
+int oracle_quadtree(otree* t, const uint32_t* mu_id, const uint32_t* mu_m, int64_t n_mu,
+                    const uint32_t* nu_id, const uint32_t* nu_m, int64_t n_nu,
+                    int32_t Q, uint64_t* out) {
+  if (check_dist(t, mu_id, mu_m, n_mu, Q) || check_dist(t, nu_id, nu_m, n_nu, Q))
+    return OR_EINVAL;
+  int64_t nt = 0;
+  int64_t* touched = cell_mass_differences(t, mu_id, mu_m, n_mu, nu_id, nu_m, n_nu, &nt);
+  if (!touched) return OR_ENOMEM;
   unsigned __int128 s = 0;
   for (int64_t i = 0; i < nt; ++i) {
     int64_t v = touched[i];
@@ -412,25 +425,9 @@ int oracle_quadtree_eps(otree* t, const uint32_t* mu_id, const uint32_t* mu_m, i
                         int32_t Q, double eps, double* out) {
   if (check_dist(t, mu_id, mu_m, n_mu, Q) || check_dist(t, nu_id, nu_m, n_nu, Q))
     return OR_EINVAL;
-  t->stamp_id++;
-  int64_t cap = (n_mu + n_nu) * (t->B + 1) + 1, nt = 0;
-  int64_t* touched = (int64_t*)malloc(cap * sizeof(int64_t));
+  int64_t nt = 0;
+  int64_t* touched = cell_mass_differences(t, mu_id, mu_m, n_mu, nu_id, nu_m, n_nu, &nt);
   if (!touched) return OR_ENOMEM;
-  for (int side = 0; side < 2; ++side) {
-    const uint32_t* id = side ? nu_id : mu_id;
-    const uint32_t* m = side ? nu_m : mu_m;
-    int64_t n = side ? n_nu : n_mu;
-    for (int64_t a = 0; a < n; ++a) {
-      for (int64_t v = t->leaf_of[id[a]]; v != 0; v = t->parent[v]) {
-        if (t->stamp[v] != t->stamp_id) {
-          t->stamp[v] = t->stamp_id;
-          t->acc[v] = 0;
-          touched[nt++] = v;
-        }
-        t->acc[v] += side ? -(int64_t)m[a] : (int64_t)m[a];
-      }
-    }
-  }
   double s = 0.0;
   for (int64_t i = 0; i < nt; ++i) {
     int64_t v = touched[i];
