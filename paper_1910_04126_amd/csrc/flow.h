@@ -255,6 +255,9 @@ __device__ int flow_match(FlowLds<C, W>& L, const int nq, const int nd, const ui
     for (int c = 0; c < C; ++c) {
       const int t = t0 + c;
       m_eta[c] = 0;
+      m_pos[c] = 0;
+      m_lo[c] = 0;
+      m_bind[c] = 0;
       if (t < n) {
         const uint32_t r = L.res[t];
         if (r > 0) {
@@ -264,6 +267,9 @@ __device__ int flow_match(FlowLds<C, W>& L, const int nq, const int nd, const ui
           const uint32_t M = Tp < Tn ? Tp : Tn;
           const uint32_t hi = isq ? L.pn[t] : L.pp[t];
           const uint32_t lo = hi - r;
+          // set for every item, owner or not: with the store only on the
+          // owner's path, builds saved wrong starts for query-owned matches
+          m_lo[c] = lo;
           if (lo < M) {
             const uint32_t* opp = isq ? L.pp : L.pn;
             int a = a0, b = e0;
@@ -286,7 +292,6 @@ __device__ int flow_match(FlowLds<C, W>& L, const int nq, const int nd, const ui
               m_pos[c] = isq ? ((uint32_t)p | ((uint32_t)t << 16)) : ((uint32_t)t | ((uint32_t)p << 16));
               if (SAVE) {
                 const uint32_t hd = isq ? ho : hi, hq = isq ? hi : ho;
-                m_lo[c] = lo;
                 m_bind[c] = (end == hd && end == hq) ? 2 : (end == hd ? 0 : 1);
               }
               ++cnt;

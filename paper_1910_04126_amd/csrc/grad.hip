@@ -47,24 +47,24 @@ struct SaveArgs {
   float* cost;  // NULL: do not price
 };
 
-template <int C, int G, int VEC>
-__global__ __launch_bounds__(64) void k_flow_save(SaveArgs a) {
-  __shared__ FlowLds<C, 1> L;
+template <int C, int W, int G, int VEC>
+__global__ __launch_bounds__(64 * W) void k_flow_save(SaveArgs a) {
+  __shared__ FlowLds<C, W> L;
   const int64_t p = blockIdx.x;
   const int64_t q = a.pair_q[p], doc = a.pair_d[p];
   const int64_t qa = a.q_off[q], da = a.d_off[doc];
   const int nq = (int)(a.q_off[q + 1] - qa), nd = (int)(a.d_off[doc + 1] - da);
-  if (nq + nd > FlowLds<C, 1>::N) {
+  if (nq + nd > FlowLds<C, W>::N) {
     if (threadIdx.x == 0) atomicOr(a.status, ERR_FLOW);
     return;
   }
   flow_stage(L, a.q_rank + qa, a.q_mass + qa, nq, a.d_rank + da, a.d_mass + da, nd);
   FlowSave sv = a.sv;
   sv.base = a.base[p];
-  const int E = flow_match<C, 1, true>(L, nq, nd, a.st, a.V, a.B, sv, a.status);
+  const int E = flow_match<C, W, true>(L, nq, nd, a.st, a.V, a.B, sv, a.status);
   if (threadIdx.x == 0) a.count[p] = E;
   if (a.cost) {
-    const double c = flow_price<C, 1, G, VEC>(L, E, nq, nd, a.X, a.perm, a.d, a.d);
+    const double c = flow_price<C, W, G, VEC>(L, E, nq, nd, a.X, a.perm, a.d, a.d);
     if (threadIdx.x == 0) a.cost[p] = (float)ldexp(c, -a.Q);
   }
 }
@@ -106,43 +106,49 @@ __global__ void k_flows_out(const int64_t* __restrict__ pair_q, const int64_t* _
   if (threadIdx.x == 0) count[p] = E;
 }
 
-// Backward of one pair on one wavefront.
+// Backward of one pair on one workgroup of BWD_THREADS threads: the saved
+// matches are sorted into the greedy's order, every match's distance and
+// coordinate gradient is computed by a group of G lanes (BWD_THREADS / G
+// matches in flight), and one lane runs the reverse sweep for the weights.
+constexpr int BWD_THREADS = 256;
+
 template <int C, int G, int VEC>
-__global__ __launch_bounds__(64) void k_flow_bwd(const int64_t* __restrict__ pair_q, const int64_t* __restrict__ pair_d,
-                                                 const int64_t* __restrict__ base, const int32_t* __restrict__ cnt,
-                                                 const uint32_t* __restrict__ fid, const uint32_t* __restrict__ feta,
-                                                 const uint64_t* __restrict__ fkey, const uint8_t* __restrict__ fbind,
-                                                 const int64_t* __restrict__ q_off, const uint32_t* __restrict__ q_rank,
-                                                 const uint16_t* __restrict__ q_pos, const int64_t* __restrict__ d_off,
-                                                 const uint32_t* __restrict__ d_rank,
-                                                 const uint16_t* __restrict__ d_pos, const uint32_t* __restrict__ perm,
-                                                 const float* __restrict__ X, int d, int Q,
-                                                 const float* __restrict__ grad_out, float* __restrict__ gX,
-                                                 float* __restrict__ gq, float* __restrict__ gd) {
+__global__ __launch_bounds__(BWD_THREADS) void k_flow_bwd(
+    const int64_t* __restrict__ pair_q, const int64_t* __restrict__ pair_d, const int64_t* __restrict__ base,
+    const int32_t* __restrict__ cnt, const uint32_t* __restrict__ fid, const uint32_t* __restrict__ feta,
+    const uint64_t* __restrict__ fkey, const uint8_t* __restrict__ fbind, const int64_t* __restrict__ q_off,
+    const uint32_t* __restrict__ q_rank, const uint16_t* __restrict__ q_pos, const int64_t* __restrict__ d_off,
+    const uint32_t* __restrict__ d_rank, const uint16_t* __restrict__ d_pos, const uint32_t* __restrict__ perm,
+    const float* __restrict__ X, int d, int Q, const float* __restrict__ grad_out, float* __restrict__ gX,
+    float* __restrict__ gq, float* __restrict__ gd) {
   constexpr int N = 64 * C;
   __shared__ uint64_t skey[N];
   __shared__ uint16_t sidx[N];
   __shared__ float sD[N];
   __shared__ double acc[N];
+  __shared__ uint32_t srow[N];  // row of X of every item: query items, then doc items
   const int64_t p = blockIdx.x;
+  const int tid = threadIdx.x;
   const float g = grad_out[p];
   const int E = cnt[p];
   const int64_t b0 = base[p];
   const int64_t qa = q_off[pair_q[p]], da = d_off[pair_d[p]];
   const int nq = (int)(q_off[pair_q[p] + 1] - qa), nd = (int)(d_off[pair_d[p] + 1] - da);
-  const int lane = lane_id();
   int P = 1;
   while (P < E) P <<= 1;
-  for (int e = lane; e < P; e += 64) {
+  for (int e = tid; e < P; e += BWD_THREADS) {
     skey[e] = e < E ? fkey[b0 + e] : ~0ull;
     sidx[e] = (uint16_t)e;
   }
-  for (int i = lane; i < nq + nd; i += 64) acc[i] = 0.0;
+  for (int i = tid; i < nq + nd; i += BWD_THREADS) {
+    acc[i] = 0.0;
+    srow[i] = perm[i < nq ? q_rank[qa + i] : d_rank[da + (i - nq)]];
+  }
   __syncthreads();
   // the greedy's order
   for (int k = 2; k <= P; k <<= 1)
     for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int t = lane; t < P; t += 64) {
+      for (int t = tid; t < P; t += BWD_THREADS) {
         const int l = t ^ j;
         if (l > t) {
           const uint64_t x = skey[t], y = skey[l];
@@ -159,8 +165,8 @@ __global__ __launch_bounds__(64) void k_flow_bwd(const int64_t* __restrict__ pai
       __syncthreads();
     }
   // distances and coordinate gradients: G lanes per match
-  const int grp = lane / G, sub = lane % G;
-  constexpr int PER = 64 / G;
+  const int grp = tid / G, sub = tid % G;
+  constexpr int PER = BWD_THREADS / G;
   const double wscale = ldexp(1.0, -Q);
   for (int r0 = 0; r0 < E; r0 += PER) {
     const int r = r0 + grp;
@@ -174,7 +180,7 @@ __global__ __launch_bounds__(64) void k_flow_bwd(const int64_t* __restrict__ pai
       const int e = sidx[r];
       const uint32_t v = fid[b0 + e];
       eta = feta[b0 + e];
-      const int64_t rowd = perm[d_rank[da + (v >> 16)]], rowq = perm[q_rank[qa + (v & 0xFFFFu)]];
+      const int64_t rowd = srow[nq + (int)(v >> 16)], rowq = srow[v & 0xFFFFu];
       if (rowd != rowq) {
         xd = X + rowd * d;
         xq = X + rowq * d;
@@ -197,7 +203,13 @@ __global__ __launch_bounds__(64) void k_flow_bwd(const int64_t* __restrict__ pai
 #pragma unroll
     for (int o = G / 2; o > 0; o >>= 1) dd += __shfl_xor(dd, o, 64);
     const float D = sqrtf(dd);
-    if (r < E && sub == 0) sD[r] = D;
+    if (r < E && sub == 0) {
+      sD[r] = D;
+      // the sort keys are dead now: keep the match's items and bind pattern
+      // in its sorted slot so the sweep below reads LDS only
+      const int e = sidx[r];
+      skey[r] = ((uint64_t)fbind[b0 + e] << 32) | fid[b0 + e];
+    }
     if (r < E && xd && D > 0.0f && gxd) {
       const float coef = (float)((double)g * (double)eta * wscale / (double)D);
       for (int i = sub; i < d; i += G) {
@@ -209,20 +221,20 @@ __global__ __launch_bounds__(64) void k_flow_bwd(const int64_t* __restrict__ pai
   }
   __syncthreads();
   // weight adjoints: reverse sweep in the greedy's order (one lane)
-  if (lane == 0) {
+  if (tid == 0) {
     for (int r = E - 1; r >= 0; --r) {
-      const int e = sidx[r];
-      const uint32_t v = fid[b0 + e];
+      const uint64_t kv = skey[r];
+      const uint32_t v = (uint32_t)kv;
       const int sd = nq + (int)(v >> 16), sq = (int)(v & 0xFFFFu);
       const double lam = (double)sD[r] - acc[sd] - acc[sq];
-      if (fbind[b0 + e] == 1) acc[sq] += lam;
+      if ((kv >> 32) == 1) acc[sq] += lam;
       else acc[sd] += lam;
     }
   }
   __syncthreads();
-  for (int i = lane; i < nq; i += 64)
+  for (int i = tid; i < nq; i += BWD_THREADS)
     if (gq) atomicAdd(gq + qa + q_pos[qa + i], (float)((double)g * acc[i]));
-  for (int i = lane; i < nd; i += 64)
+  for (int i = tid; i < nd; i += BWD_THREADS)
     if (gd) atomicAdd(gd + da + d_pos[da + i], (float)((double)g * acc[nq + i]));
 }
 
@@ -240,10 +252,10 @@ __global__ void k_copy_or_compare(const uint8_t* __restrict__ a, uint8_t* __rest
 
 // ------------------------------------------------------------- dispatch --
 
-#define FT_DISPATCH_CG(KERNEL, cls, G, VEC, grid, s, ...)                                    \
+#define FT_DISPATCH_CG(KERNEL, cls, G, VEC, grid, block, s, ...)                             \
   do {                                                                                       \
     auto go = [&](auto cc, auto gg, auto vv) {                                              \
-      KERNEL<decltype(cc)::value, decltype(gg)::value, decltype(vv)::value><<<grid, 64, 0, s>>>(__VA_ARGS__); \
+      KERNEL<decltype(cc)::value, decltype(gg)::value, decltype(vv)::value><<<grid, block, 0, s>>>(__VA_ARGS__); \
     };                                                                                       \
     auto gsel = [&](auto cc, auto vv) {                                                      \
       switch (G) {                                                                           \
@@ -264,6 +276,39 @@ __global__ void k_copy_or_compare(const uint8_t* __restrict__ a, uint8_t* __rest
       case 2: vsel(std::integral_constant<int, 8>{}); break;                                 \
       case 3: vsel(std::integral_constant<int, 16>{}); break;                                \
       default: vsel(std::integral_constant<int, 32>{}); break;                               \
+    }                                                                                        \
+  } while (0)
+
+// The saving kernel in the size class's shape (C items per lane, W wavefronts).
+#define FT_DISPATCH_SAVE(cls, G, VEC, grid, s, ...)                                          \
+  do {                                                                                       \
+    auto go = [&](auto cc, auto ww, auto gg, auto vv) {                                     \
+      k_flow_save<decltype(cc)::value, decltype(ww)::value, decltype(gg)::value, decltype(vv)::value> \
+          <<<grid, 64 * decltype(ww)::value, 0, s>>>(__VA_ARGS__);                           \
+    };                                                                                       \
+    auto gsel = [&](auto cc, auto ww, auto vv) {                                             \
+      switch (G) {                                                                           \
+        case 1: go(cc, ww, std::integral_constant<int, 1>{}, vv); break;                     \
+        case 2: go(cc, ww, std::integral_constant<int, 2>{}, vv); break;                     \
+        case 4: go(cc, ww, std::integral_constant<int, 4>{}, vv); break;                     \
+        case 8: go(cc, ww, std::integral_constant<int, 8>{}, vv); break;                     \
+        default: go(cc, ww, std::integral_constant<int, 16>{}, vv); break;                   \
+      }                                                                                      \
+    };                                                                                       \
+    auto vsel = [&](auto cc, auto ww) {                                                      \
+      if (VEC == 4) gsel(cc, ww, std::integral_constant<int, 4>{});                          \
+      else gsel(cc, ww, std::integral_constant<int, 1>{});                                   \
+    };                                                                                       \
+    using I = std::integral_constant<int, 1>;                                                \
+    using I2 = std::integral_constant<int, 2>;                                               \
+    using I4 = std::integral_constant<int, 4>;                                               \
+    using I8 = std::integral_constant<int, 8>;                                               \
+    switch (cls) {                                                                           \
+      case 0: vsel(I2{}, I{}); break;                                                        \
+      case 1: vsel(I4{}, I{}); break;                                                        \
+      case 2: vsel(I4{}, I2{}); break;                                                       \
+      case 3: vsel(I4{}, I4{}); break;                                                       \
+      default: vsel(I8{}, I4{}); break;                                                      \
     }                                                                                        \
   } while (0)
 
@@ -312,7 +357,7 @@ static int run_save(ft_index* ix, const float* X, const int64_t* q_off, const ui
   a.cost = cost;
   const int G = lanes_for((ix->d + 3) / 4);
   const int VEC = (X && ix->d % 4 == 0 && ((uintptr_t)X & 15) == 0) ? 4 : 1;
-  FT_DISPATCH_CG(k_flow_save, cls, G, VEC, dim3((unsigned)n_pairs), s, a);
+  FT_DISPATCH_SAVE(cls, G, VEC, dim3((unsigned)n_pairs), s, a);
   FT_HIP(hipGetLastError());
   ix->fwd_pairs = n_pairs;
   ix->fwd_cap = total;
@@ -400,7 +445,7 @@ extern "C" ft_status ft_flowtree_cost_grad(ft_index* ix, const float* X, const i
     const int cls = class_for(ix->qry.max_size + ix->docs.max_size);
     const int G = lanes_for((ix->d + 3) / 4);
     const int VEC = (ix->d % 4 == 0 && ((uintptr_t)X & 15) == 0) ? 4 : 1;
-    FT_DISPATCH_CG(k_flow_bwd, cls, G, VEC, dim3((unsigned)n_pairs), s, pair_q, pair_d, ix->fwd_base.as<int64_t>(),
+    FT_DISPATCH_CG(k_flow_bwd, cls, G, VEC, dim3((unsigned)n_pairs), BWD_THREADS, s, pair_q, pair_d, ix->fwd_base.as<int64_t>(),
                    ix->fwd_cnt.as<int32_t>(), ix->fwd_id.as<uint32_t>(), ix->fwd_eta.as<uint32_t>(),
                    ix->fwd_key.as<uint64_t>(), ix->fwd_bind.as<uint8_t>(), ix->qry.off.as<int64_t>(),
                    ix->qry.rank.as<uint32_t>(), ix->qry.pos.as<uint16_t>(), ix->docs.off.as<int64_t>(),

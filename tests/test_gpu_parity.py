@@ -326,17 +326,17 @@ def test_flowtree_deterministic(ft):
 
 # ------------------------------------------------------------- gradients --
 
-def test_cost_grad_vs_oracle(ft):
-    say("cost_grad: V=3000 d=300, 24 pairs, forward and backward")
-    ds = gen.make("grad", V=3000, n_pairs=24)
+def check_cost_grad(ft, ds, pq, pd, g_lo, g_hi):
+    """Forward costs and the backward (X, query weights, doc weights) of
+    sum_p g_p cost_p against the oracle's Flowtree and its float64 frozen
+    gradient."""
     ix = build_index(ft, ds)
     T = oracle_tree(ds)
-    pq, pd = ds.extra["pair_q"], ds.extra["pair_d"]
     X = t(ds.X)
     qo, qi, qm = queries(ds)
     cost = torch.empty(len(pq), dtype=torch.float32, device=X.device)
     ft.flowtree_cost_grad(ix, X, qo, qi, qm, t(pq), t(pd), ft.FT_FWD, cost=cost)
-    g_out = torch.linspace(0.5, 1.5, len(pq), device=X.device, dtype=torch.float32)
+    g_out = torch.linspace(g_lo, g_hi, len(pq), device=X.device, dtype=torch.float32)
     gX = torch.zeros_like(X)
     gq = torch.zeros(len(ds.q_id), device=X.device)
     gd = torch.zeros(len(ds.doc_id), device=X.device)
@@ -359,9 +359,51 @@ def test_cost_grad_vs_oracle(ft):
     rows = np.flatnonzero(np.abs(wX).sum(1) > 0)
     for r in rows:
         assert np.linalg.norm(gX[r] - wX[r]) <= 1e-5 * np.linalg.norm(wX[r]) + 1e-7
-    assert np.abs(gX[np.setdiff1d(np.arange(len(wX)), rows)]).max() == 0
+    untouched = np.setdiff1d(np.arange(len(wX)), rows)
+    assert (gX[untouched] == 0).all()
     assert np.allclose(gq, wq, rtol=1e-5, atol=1e-6 * np.abs(wq).max())
     assert np.allclose(gd, wd, rtol=1e-5, atol=1e-6 * np.abs(wd).max())
+
+
+def test_cost_grad_vs_oracle(ft):
+    say("cost_grad: V=3000 d=300, 24 pairs, forward and backward")
+    ds = gen.make("grad", V=3000, n_pairs=24)
+    check_cost_grad(ft, ds, ds.extra["pair_q"], ds.extra["pair_d"], 0.5, 1.5)
+
+
+@pytest.mark.parametrize("hi,d", [(60, 30), (120, 32), (250, 30), (500, 32), (1000, 30)])
+def test_cost_grad_size_classes(ft, hi, d):
+    """Forward and backward in every size class (the largest pair of a call
+    picks the workgroup shape: up to 128, 256, 512, 1024 and 2048 items),
+    with rows of d = 30 (scalar loads) and d = 32 (float4 loads); some
+    queries share points with their docs, and one pair is a distribution
+    against itself (every match a zero-length self-match)."""
+    say("cost_grad size class: supports up to %d, d=%d" % (hi, d))
+    rng = np.random.default_rng(900 + hi)
+    X = rng.standard_normal((3000, d)).astype(np.float32)
+    X[10:14] = X[5]  # coincident points under different ids
+    ds = dataset_on(X, gen.random_shift(rng, d, 30), 30, 6, 4, max(1, hi // 3), hi, 24, hi)
+    # query 0 is doc 0 itself; query 1 shares half of doc 1's points
+    do, di, dm = ds.doc_off, ds.doc_id.copy(), ds.doc_mass
+    qo, qi, qm = ds.q_off, ds.q_id.copy(), ds.q_mass
+    n0 = do[1] - do[0]
+    qsz = np.diff(qo)
+    qsz[0] = n0
+    nqo = np.zeros(len(qsz) + 1, np.int64)
+    nqo[1:] = np.cumsum(qsz)
+    nqi = np.concatenate([di[do[0]:do[1]]] + [qi[qo[j]:qo[j + 1]] for j in range(1, len(qsz))]).astype(np.uint32)
+    a1, b1 = do[1], do[2]
+    share = di[a1:a1 + (b1 - a1) // 2]
+    q1 = nqi[nqo[1]:nqo[2]]
+    keep = np.setdiff1d(q1, share)[: max(0, len(q1) - len(share))]
+    q1 = np.concatenate([share, keep])[: len(q1)]
+    assert len(np.unique(q1)) == len(q1)
+    nqi[nqo[1]:nqo[2]] = q1
+    nqm = gen.uniform_masses(nqo, nqi, 24)
+    ds = gen.Dataset("custom", X, ds.shift, 30, 24, do, di, dm, nqo, nqi, nqm, 5)
+    pq = np.array([0, 1, 2, 3, 0, 1, 2, 3, 3], np.int64)
+    pd = np.array([0, 1, 2, 3, 4, 5, 5, 4, 0], np.int64)
+    check_cost_grad(ft, ds, pq, pd, 0.25, 2.0)
 
 
 def test_autograd_function(ft):
