@@ -51,7 +51,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 TRAFFIC_BYTES = 2.464e+11
 TRAFFIC_SOURCES = ("paper_1910_04126_amd/csrc/flow.h", "paper_1910_04126_amd/csrc/flowtree.hip",
                    "paper_1910_04126_amd/csrc/wave.h", "paper_1910_04126_amd/csrc/common.h")
-TRAFFIC_SOURCES_SHA1 = "10ef73b6d0a9431b5f9f6bc0244c09bc9f19c9f0"
+TRAFFIC_SOURCES_SHA1 = "5a3386d6472639727828a9e88f0f77e9c5b8517d"
 
 
 def measured_traffic(workload):
