@@ -29,7 +29,7 @@ Contents, each following the paper:
   4.1, regularisation of Appendix "Sinkhorn regularization parameter"),
   float64.
 
-Parity of the GPU path is judged against these functions.  Functions with no
+Parity of the GPU path is checked against these functions.  Functions with no
 independent pin are marked "parity unpinned" in their docstring.
 """
 from __future__ import annotations
