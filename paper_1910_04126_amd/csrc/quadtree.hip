@@ -126,19 +126,22 @@ __global__ __launch_bounds__(QT_THREADS) void k_qt_tile(
 // A workgroup takes one (query, slice): it looks up up to QP_ENTRIES of the
 // query's cells at a time in the slice directory, cuts the non-empty lists
 // into pieces of QP_PIECE entries (a table in LDS maps each piece to its
-// list), and its wavefronts, two pieces at a time, add
+// list), and its wavefronts, QP_U pieces at a time, add
 // side(depth) * min(query mass, doc mass) into one LDS counter per doc; the
 // keys S_q + S_d - 2 * counter follow.  Counters are u32 in units of the
 // deepest side when every sum fits (Q + height <= 32: a depth's cells
 // partition the mass, so the sum is below 2^(Q + height)), else u64 in grid
-// units; either way they fill 32 KB, so a slice is 8192 or 4096 docs.
+// units; either way they fill 32 KB, so a slice is 8192 or 4096 docs.  With
+// 128 cells per round and two pieces in flight a workgroup needs under 40 KB
+// of LDS and 46 VGPRs, so a CU holds four of them (8 wavefronts per SIMD):
+// the kernel spends most of its time waiting on list reads and LDS atomics.
 
 constexpr int QP_THREADS = 512;
 constexpr int QP_WAVES = QP_THREADS / 64;
 constexpr int QP_ACC_BYTES = 32 * 1024;
-constexpr int QP_ENTRIES = 256;  // query cells per round (an item index fits a byte)
+constexpr int QP_ENTRIES = 128;  // query cells per round (an item index fits a byte)
 constexpr int QP_PIECE = 256;    // list entries per piece
-constexpr int QP_U = 4;          // pieces in flight per wavefront
+constexpr int QP_U = 2;          // pieces in flight per wavefront
 // a list in a slice has at most one entry per doc
 constexpr int QP_MAX_PIECES = QP_ENTRIES * (QP_ACC_BYTES / 4) / QP_PIECE;
 
