@@ -16,6 +16,13 @@ __device__ __forceinline__ uint64_t sort_bits(float c) {
   uint32_t b = __float_as_uint(c);
   return b == 0x80000000u ? 0ull : (uint64_t)b;
 }
+// sort_bits of a 4-byte key given by its bit pattern
+template <class K>
+__device__ __forceinline__ uint64_t sort_bits_of(uint32_t b);
+template <>
+__device__ __forceinline__ uint64_t sort_bits_of<uint32_t>(uint32_t b) { return (uint64_t)b; }
+template <>
+__device__ __forceinline__ uint64_t sort_bits_of<float>(uint32_t b) { return sort_bits(__uint_as_float(b)); }
 __device__ __forceinline__ void store_key(uint64_t* out, uint64_t b) { *out = b; }
 __device__ __forceinline__ void store_key(uint32_t* out, uint64_t b) { *out = (uint32_t)b; }
 __device__ __forceinline__ void store_key(float* out, uint64_t b) { *out = __uint_as_float((uint32_t)b); }
@@ -208,8 +215,7 @@ __global__ __launch_bounds__(1024) void k_topk_window(const K* __restrict__ keys
     digit_levels(rk, ns, target, 16u, hs, sel, below, nties, hist, &s_b, &s_below);
     if (threadIdx.x == 0) s_nl = 0;
     __syncthreads();
-    for (int64_t c = threadIdx.x; c < n; c += blockDim.x) {
-      const uint64_t x = sort_bits(rk[c]);
+    auto collect = [&](uint64_t x, int64_t c) {
       if (shr64(x, hs) <= sel) {
         const uint32_t p = atomicAdd(&s_nl, 1u);
         if (p < (uint32_t)COLLECT_CAP) {
@@ -217,7 +223,24 @@ __global__ __launch_bounds__(1024) void k_topk_window(const K* __restrict__ keys
           bufd[p] = (uint32_t)c;
         }
       }
+    };
+    bool done = false;
+    if constexpr (sizeof(K) == 4) {
+      // 4-byte keys of a 16-byte aligned row: four per load
+      if ((n & 3) == 0 && (reinterpret_cast<uintptr_t>(rk) & 15) == 0) {
+        const uint4* r4 = reinterpret_cast<const uint4*>(rk);
+        for (int64_t c = threadIdx.x; c < (n >> 2); c += blockDim.x) {
+          const uint4 v = r4[c];
+          collect(sort_bits_of<K>(v.x), 4 * c);
+          collect(sort_bits_of<K>(v.y), 4 * c + 1);
+          collect(sort_bits_of<K>(v.z), 4 * c + 2);
+          collect(sort_bits_of<K>(v.w), 4 * c + 3);
+        }
+        done = true;
+      }
     }
+    if (!done)
+      for (int64_t c = threadIdx.x; c < n; c += blockDim.x) collect(sort_bits(rk[c]), c);
     __syncthreads();
     const uint32_t got = s_nl;
     if (got >= (uint32_t)k && got <= (uint32_t)COLLECT_CAP) {
