@@ -101,10 +101,26 @@ __device__ void digit_levels(const K* __restrict__ rk, int64_t n_cols, uint32_t 
     const uint32_t dmask = (1u << (hs - lo)) - 1u;
     for (int b = threadIdx.x; b < (1 << W); b += blockDim.x) hist[b] = 0;
     __syncthreads();
-    for (int64_t c = threadIdx.x; c < n_cols; c += blockDim.x) {
-      const uint64_t x = sort_bits(rk[c]);
+    auto count = [&](uint64_t x) {
       if (shr64(x, hs) == sel) atomicAdd(&hist[(uint32_t)(x >> lo) & dmask], 1u);
+    };
+    bool done = false;
+    if constexpr (sizeof(K) == 4) {
+      // 4-byte keys of a 16-byte aligned prefix: four per load
+      if ((n_cols & 3) == 0 && (reinterpret_cast<uintptr_t>(rk) & 15) == 0) {
+        const uint4* r4 = reinterpret_cast<const uint4*>(rk);
+        for (int64_t c = threadIdx.x; c < (n_cols >> 2); c += blockDim.x) {
+          const uint4 v = r4[c];
+          count(sort_bits_of<K>(v.x));
+          count(sort_bits_of<K>(v.y));
+          count(sort_bits_of<K>(v.z));
+          count(sort_bits_of<K>(v.w));
+        }
+        done = true;
+      }
     }
+    if (!done)
+      for (int64_t c = threadIdx.x; c < n_cols; c += blockDim.x) count(sort_bits(rk[c]));
     __syncthreads();
     if (threadIdx.x < 64) {
       const int per = (1 << W) / 64;
