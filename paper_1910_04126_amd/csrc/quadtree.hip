@@ -555,6 +555,15 @@ extern "C" ft_status ft_quadtree_knn(ft_index* ix, const int64_t* q_off, const u
     }
     unsigned long long* minmax_base =
         cand ? nullptr : (unsigned long long*)ix->ws_sel.ensure(rows_per_chunk * 16 * (pipe ? 2 : 1));
+    // the per-row key ranges start empty; with several chunks, the select
+    // stream empties a buffer again right after its select has read it, so
+    // no clearing kernel waits for a CU between two ranking launches
+    if (minmax_base) {
+      const int64_t mm_rows = rows_per_chunk * (pipe ? 2 : 1);
+      k_minmax_init<<<(unsigned)ceil_div(mm_rows, 256), 256, 0, s>>>(minmax_base, mm_rows);
+      FT_HIP(hipGetLastError());
+    }
+    const int64_t n_chunks = ceil_div(n_q, rows_per_chunk);
     int64_t chunk = 0;
     for (int64_t r0 = 0; r0 < n_q; r0 += rows_per_chunk, ++chunk) {
       const int64_t r1 = std::min(n_q, r0 + rows_per_chunk);
@@ -566,9 +575,9 @@ extern "C" ft_status ft_quadtree_knn(ft_index* ix, const int64_t* q_off, const u
         const int64_t rows = r1 - r0, groups = ceil_div(ix->post_nsl, 8);
         FT_REQUIRE(groups * 8 * rows < (int64_t(1) << 31), FT_ERANGE, "too many (query, slice) workgroups");
         minmax = minmax_base + b * rows_per_chunk * 2;
-        // the buffers of chunk - 2 must have been read by its select
+        // the buffers of chunk - 2 must have been read by its select (and
+        // the key ranges emptied again)
         if (pipe && chunk >= 2) FT_HIP(hipStreamWaitEvent(s, ix->ev_sel[b], 0));
-        k_minmax_init<<<(unsigned)ceil_div(rows, 256), 256, 0, s>>>(minmax, rows);
         auto go = [&](auto narrow, auto packed) {
           k_qt_post<decltype(narrow)::value, decltype(packed)::value><<<(unsigned)(groups * 8 * rows), QP_THREADS, 0, s>>>(
               ix->post.as<uint16_t>(),
@@ -619,6 +628,10 @@ extern "C" ft_status ft_quadtree_knn(ft_index* ix, const int64_t* q_off, const u
       else
         topk_rows(keys, r1 - r0, n_cols, cand ? cand + r0 * n_cols : nullptr, k, out_key + r0 * k, out_doc + r0 * k,
                   s_sel, reinterpret_cast<const uint64_t*>(minmax));
+      if (minmax && pipe && chunk + 2 < n_chunks) {
+        k_minmax_init<<<(unsigned)ceil_div(rows_per_chunk, 256), 256, 0, s_sel>>>(minmax, rows_per_chunk);
+        FT_HIP(hipGetLastError());
+      }
       if (pipe) FT_HIP(hipEventRecord(ix->ev_sel[b], s_sel));
     }
     if (pipe) {
