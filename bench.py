@@ -48,7 +48,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 # workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a 1 GiB copy
 # (profiles/flowtree_batched_uneven_hbm_traffic.md), valid while the kernel
 # sources hash to TRAFFIC_SOURCES_SHA1.
-TRAFFIC_BYTES = 2.787e+11
+TRAFFIC_BYTES = 2.783e+11
 TRAFFIC_SOURCES = ("paper_1910_04126_amd/csrc/flow.h", "paper_1910_04126_amd/csrc/flowtree.hip",
                    "paper_1910_04126_amd/csrc/wave.h", "paper_1910_04126_amd/csrc/common.h")
 TRAFFIC_SOURCES_SHA1 = "702b6f3941dd9d237625072ec6c946b0a9a13b4f"

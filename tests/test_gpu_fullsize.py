@@ -83,6 +83,31 @@ def test_batched_full(ft):
     assert swaps <= 2
 
 
+def test_batched_prune_chunks(ft):
+    """The 4096 queries of the batched workload twice over rank all 1M docs
+    in four chunks of 2048 queries: two key buffers in turn, each one's key
+    ranges cleared again by the select stream before its next chunk.  Both
+    copies of every query must get the same top-1000 keys and docs, and a
+    query of the last chunk must match the oracle's exact Quadtree top-k."""
+    say("full size: 1M docs, the 4096 batched queries twice (four prune chunks), top-1000")
+    ds = gen.make("batched")
+    ix = build_index(ft, ds)
+    nq = ds.n_queries
+    off2 = np.concatenate([ds.q_off, ds.q_off[1:] + ds.q_off[-1]]).astype(np.int64)
+    keys, cand = ft.quadtree_knn(ix, t(off2), t(np.tile(ds.q_id, 2)), t(np.tile(ds.q_mass, 2)), 1000)
+    torch.cuda.synchronize()
+    keys, cand = keys.cpu().numpy().view(np.uint64), cand.cpu().numpy()
+    assert keys.shape == (2 * nq, 1000)
+    assert np.array_equal(keys[:nq], keys[nq:])
+    assert np.array_equal(cand[:nq], cand[nq:])
+    q = nq - 5  # in the fourth chunk as query 2 * nq - 5
+    say("  query %d: oracle Quadtree over %d docs" % (q, ds.n_docs))
+    T = oracle_tree(ds)
+    all_docs = np.arange(ds.n_docs)
+    M = oracle_matrix(T, ds, [q], all_docs, "qt")[0]
+    check_topk(cand[nq + q], keys[nq + q], M, all_docs, 1000, exact=True)
+
+
 def test_image_full(ft):
     say("full size: image-shaped, 60k docs, 1000 queries, Flowtree over all docs, top-10")
     ds = gen.make("image")
