@@ -498,9 +498,12 @@ def test_random_model_against_oracle(ft, N, s, eps, reps):
 
 # ------------------------------------------------------- long-row select --
 
-def test_long_rows_select(ft):
-    say("select: 6000 docs ranked in full (window select), quadtree and flowtree")
-    ds = gen.make("text", V=4000, d=64, n_docs=6000, n_queries=3)
+@pytest.mark.parametrize("n_docs", [6000, 6001, 6003])
+def test_long_rows_select(ft, n_docs):
+    """Rows of 6000 keys are read four keys per load; rows of 6001 and 6003
+    keys (not a multiple of four) one key per load."""
+    say("select: %d docs ranked in full (window select), quadtree and flowtree" % n_docs)
+    ds = gen.make("text", V=4000, d=64, n_docs=n_docs, n_queries=3)
     ix = build_index(ft, ds)
     T = oracle_tree(ds)
     docs = np.arange(ds.n_docs)
