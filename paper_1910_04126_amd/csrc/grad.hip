@@ -110,7 +110,7 @@ __global__ void k_flows_out(const int64_t* __restrict__ pair_q, const int64_t* _
 // matches are sorted into the greedy's order, every match's distance and
 // coordinate gradient is computed by a group of G lanes (BWD_THREADS / G
 // matches in flight), and one lane runs the reverse sweep for the weights.
-constexpr int BWD_THREADS = 256;
+constexpr int BWD_THREADS = 1024;
 
 template <int C, int G, int VEC>
 __global__ __launch_bounds__(BWD_THREADS) void k_flow_bwd(
