@@ -171,6 +171,7 @@ def build_tree(X, shift, B, doc_off, doc_id, doc_mass, Q) -> Index:
     ix = Index(h, V, d, doc_off.numel() - 1)
     ix.doc_sizes = doc_off[1:] - doc_off[:-1]
     ix.doc_nnz = doc_id.numel()
+    ix.doc_mass = doc_mass.clone()  # the weights autograd.FlowtreeCost checks d_w against
     ix.Q = Q
     return ix
 

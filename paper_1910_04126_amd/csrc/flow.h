@@ -385,7 +385,8 @@ __device__ __forceinline__ double row_sum_f64(double v) {
 // schedule.  The result is valid in wavefront 0.
 template <int C, int W, int G, int VEC>
 __device__ double flow_price(FlowLds<C, W>& L, const int E, const int nq, const int nd, const float* __restrict__ X,
-                             const uint32_t* __restrict__ row_of_rank, const int stride, const int d) {
+                             const uint32_t* __restrict__ row_of_rank, const int stride, const int d,
+                             uint32_t* __restrict__ status) {
   constexpr int PER = 64 * W / G;
   constexpr int PV = C * W >= 8 ? 5 : 2;
   using V4 = typename std::conditional<VEC == 4, float4, float>::type;
@@ -487,7 +488,11 @@ __device__ double flow_price(FlowLds<C, W>& L, const int E, const int nq, const 
       }
       units = (int)(all >> 1);
     }
-    if (2 * units > 3 * FlowLds<C, W>::N / 2) units = 0;  // cannot happen (see above); never overrun
+    if (2 * units > 3 * FlowLds<C, W>::N / 2) {
+      // cannot happen (see above); never overrun, report it instead
+      if (tid == 0) atomicOr(status, ERR_FLOW);
+      units = 0;
+    }
     for (int i = tid; i < 2 * units; i += 64 * W) ord[i] = NONE;
     __syncthreads();
     for (int e = tid; e < E; e += 64 * W) {

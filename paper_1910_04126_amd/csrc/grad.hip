@@ -64,7 +64,7 @@ __global__ __launch_bounds__(64 * W) void k_flow_save(SaveArgs a) {
   const int E = flow_match<C, W, true>(L, nq, nd, a.st, a.V, a.B, sv, a.status);
   if (threadIdx.x == 0) a.count[p] = E;
   if (a.cost) {
-    const double c = flow_price<C, W, G, VEC>(L, E, nq, nd, a.X, a.perm, a.d, a.d);
+    const double c = flow_price<C, W, G, VEC>(L, E, nq, nd, a.X, a.perm, a.d, a.d, a.status);
     if (threadIdx.x == 0) a.cost[p] = (float)ldexp(c, -a.Q);
   }
 }

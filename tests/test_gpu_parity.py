@@ -326,12 +326,43 @@ def test_flowtree_deterministic(ft):
 
 # ------------------------------------------------------------- gradients --
 
+def oracle_weighted_grad(ds, pq, pd, g_out):
+    """Oracle Flowtree costs of the pairs and the float64 frozen gradient of
+    sum_p g_out[p] cost_p in X, the query weights and the doc weights."""
+    T = oracle_tree(ds)
+    costs = np.empty(len(pq))
+    wX = np.zeros(ds.X.shape)
+    wq = np.zeros(len(ds.q_id))
+    wd = np.zeros(len(ds.doc_id))
+    for p, (q, doc) in enumerate(zip(pq, pd)):
+        a, b = ds.doc_off[doc], ds.doc_off[doc + 1]
+        qa, qb = ds.q_off[q], ds.q_off[q + 1]
+        costs[p], fl = T.flowtree(ds.doc_id[a:b], ds.doc_mass[a:b], ds.q_id[qa:qb], ds.q_mass[qa:qb], Q=ds.Q)
+        gx, gm, gn = oracle.frozen_grad(ds.X, ds.doc_id[a:b], ds.q_id[qa:qb], fl,
+                                        ds.doc_mass[a:b] / 2.0 ** ds.Q, ds.q_mass[qa:qb] / 2.0 ** ds.Q)
+        wX += g_out[p] * gx
+        wd[a:b] += g_out[p] * gm
+        wq[qa:qb] += g_out[p] * gn
+    return costs, wX, wq, wd
+
+
+def assert_grads_close(gX, gq, gd, wX, wq, wd):
+    """1e-5 relative in norm per nonzero row of dX; rows the oracle leaves
+    at zero stay exactly zero; weight gradients 1e-5 relative."""
+    rows = np.flatnonzero(np.abs(wX).sum(1) > 0)
+    for r in rows:
+        assert np.linalg.norm(gX[r] - wX[r]) <= 1e-5 * np.linalg.norm(wX[r]) + 1e-7, "row %d" % r
+    untouched = np.setdiff1d(np.arange(len(wX)), rows)
+    assert (gX[untouched] == 0).all()
+    assert np.allclose(gq, wq, rtol=1e-5, atol=1e-6 * np.abs(wq).max())
+    assert np.allclose(gd, wd, rtol=1e-5, atol=1e-6 * np.abs(wd).max())
+
+
 def check_cost_grad(ft, ds, pq, pd, g_lo, g_hi):
     """Forward costs and the backward (X, query weights, doc weights) of
     sum_p g_p cost_p against the oracle's Flowtree and its float64 frozen
     gradient."""
     ix = build_index(ft, ds)
-    T = oracle_tree(ds)
     X = t(ds.X)
     qo, qi, qm = queries(ds)
     cost = torch.empty(len(pq), dtype=torch.float32, device=X.device)
@@ -343,26 +374,9 @@ def check_cost_grad(ft, ds, pq, pd, g_lo, g_hi):
     ft.flowtree_cost_grad(ix, X, qo, qi, qm, t(pq), t(pd), ft.FT_BWD, grad_out=g_out, grad_X=gX,
                           grad_qmass=gq, grad_dmass=gd)
     cost, gX, gq, gd, g_out = [v.cpu().numpy() for v in (cost, gX, gq, gd, g_out)]
-    wX = np.zeros(ds.X.shape)
-    wq = np.zeros(len(ds.q_id))
-    wd = np.zeros(len(ds.doc_id))
-    for p, (q, doc) in enumerate(zip(pq, pd)):
-        a, b = ds.doc_off[doc], ds.doc_off[doc + 1]
-        qa, qb = ds.q_off[q], ds.q_off[q + 1]
-        c, fl = T.flowtree(ds.doc_id[a:b], ds.doc_mass[a:b], ds.q_id[qa:qb], ds.q_mass[qa:qb], Q=ds.Q)
-        assert abs(cost[p] - c) <= 1e-5 * c
-        gx, gm, gn = oracle.frozen_grad(ds.X, ds.doc_id[a:b], ds.q_id[qa:qb], fl,
-                                        ds.doc_mass[a:b] / 2.0 ** ds.Q, ds.q_mass[qa:qb] / 2.0 ** ds.Q)
-        wX += g_out[p] * gx
-        wd[a:b] += g_out[p] * gm
-        wq[qa:qb] += g_out[p] * gn
-    rows = np.flatnonzero(np.abs(wX).sum(1) > 0)
-    for r in rows:
-        assert np.linalg.norm(gX[r] - wX[r]) <= 1e-5 * np.linalg.norm(wX[r]) + 1e-7
-    untouched = np.setdiff1d(np.arange(len(wX)), rows)
-    assert (gX[untouched] == 0).all()
-    assert np.allclose(gq, wq, rtol=1e-5, atol=1e-6 * np.abs(wq).max())
-    assert np.allclose(gd, wd, rtol=1e-5, atol=1e-6 * np.abs(wd).max())
+    want, wX, wq, wd = oracle_weighted_grad(ds, pq, pd, g_out)
+    assert (np.abs(cost - want) <= 1e-5 * want).all()
+    assert_grads_close(gX, gq, gd, wX, wq, wd)
 
 
 def test_cost_grad_vs_oracle(ft):
@@ -407,19 +421,45 @@ def test_cost_grad_size_classes(ft, hi, d):
 
 
 def test_autograd_function(ft):
-    say("autograd: FlowtreeCost backward equals the C ABI backward")
+    """FlowtreeCost through torch.autograd: the forward values and the
+    gradients in X, q_w and d_w of sum_p g_p cost_p (g non-uniform) against
+    the oracle's Flowtree and its float64 frozen gradient; a second forward
+    on other pairs between a forward and its backward changes nothing; q_w
+    and d_w that do not equal the masses / 2^Q are rejected."""
+    say("autograd: FlowtreeCost values and gradients against the oracle")
     from paper_1910_04126_amd.autograd import flowtree_cost
-    ds = gen.make("grad", V=2000, n_pairs=8)
+    ds = gen.make("grad", V=2000, n_pairs=12)
     ix = build_index(ft, ds)
     qo, qi, qm = queries(ds)
+    pq_h = np.concatenate([np.arange(12), [4]]).astype(np.int64)
+    pd_h = np.concatenate([np.roll(np.arange(12), 5), [9]]).astype(np.int64)
+    pq, pd = t(pq_h), t(pd_h)
     X = t(ds.X).requires_grad_(True)
     qw = (t(ds.q_mass.astype(np.float64)) * 2.0 ** -ds.Q).to(torch.float32).requires_grad_(True)
     dw = (t(ds.doc_mass.astype(np.float64)) * 2.0 ** -ds.Q).to(torch.float32).requires_grad_(True)
-    pq, pd = t(ds.extra["pair_q"]), t(ds.extra["pair_d"])
+    g = torch.linspace(-0.7, 1.9, len(pq_h), device=X.device, dtype=torch.float32)
     c = flowtree_cost(X, qw, dw, ix, qo, qi, qm, pq, pd)
-    c.sum().backward()
-    assert X.grad is not None and torch.isfinite(X.grad).all()
-    assert qw.grad is not None and dw.grad is not None
+    # another forward, on a different pair list, before the first backward
+    other = flowtree_cost(X, qw, dw, ix, qo, qi, qm, pq.flip(0)[:5].contiguous(), pd[:5].contiguous())
+    assert other.shape == (5,)
+    (c * g).sum().backward()
+    want, wX, wq, wd = oracle_weighted_grad(ds, pq_h, pd_h, g.cpu().numpy().astype(np.float64))
+    got = c.detach().cpu().numpy()
+    assert (np.abs(got - want) <= 1e-5 * want).all()
+    assert qw.grad.dtype == torch.float32 and dw.grad.dtype == torch.float32
+    assert_grads_close(X.grad.cpu().numpy(), qw.grad.cpu().numpy(), dw.grad.cpu().numpy(), wX, wq, wd)
+    assert np.abs(wq).max() > 0 and np.abs(wd).max() > 0
+    # weights that are not the masses / 2^Q
+    bad_d = dw.detach().clone()
+    bad_d[3] += 2.0 ** -ds.Q
+    with pytest.raises(ValueError, match="d_w"):
+        flowtree_cost(X, qw, bad_d, ix, qo, qi, qm, pq, pd)
+    bad_q = qw.detach().clone()
+    bad_q[0] *= 0.5
+    with pytest.raises(ValueError, match="q_w"):
+        flowtree_cost(X, bad_q, dw, ix, qo, qi, qm, pq, pd)
+    with pytest.raises(ValueError, match="d_w"):
+        flowtree_cost(X, qw, dw[:-1], ix, qo, qi, qm, pq, pd)
 
 
 # ------------------------------------------------------------------ errors --
@@ -579,9 +619,10 @@ def test_long_rows_refined_bucket(ft):
 
 def test_long_rows_many_ties(ft):
     """Thousands of identical docs give thousands of equal keys at the k-th
-    position: the window select hands the row to the radix fallback, and
-    ties must still go to the lowest doc indices."""
-    say("select: 5000 docs, 4200 identical (fallback path)")
+    position: the one-pass gather overflows, the exact path's bucket of the
+    k-th key stays too large to refine, and the in-order scan over the equal
+    keys must give the ties to the lowest doc indices."""
+    say("select: 5000 docs, 4200 identical (in-order tie scan)")
     base = gen.make("tiny", n_docs=800, n_queries=2)
     reps = 4200
     one = base.doc_id[base.doc_off[0]:base.doc_off[1]]
