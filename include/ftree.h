@@ -143,6 +143,32 @@ ft_status ft_flowtree_knn(ft_index* index, const int64_t* q_off, const uint32_t*
                           int64_t* out_doc, void* stream);
 
 /* ------------------------------------------------------------------------
+ * ft_flowtree_knn_noalloc -- ft_flowtree_knn over candidate lists for callers
+ * that cannot allocate device memory (tight serving loops, harnesses that
+ * forbid hipMalloc).
+ *
+ * Arguments and results as ft_flowtree_knn with a candidate list (cand must
+ * not be NULL); the output equals ft_flowtree_knn's bit for bit.  The call
+ * allocates nothing: the prepared queries, the candidate costs and the
+ * status words live in one static device array of about 7.8 MB per GPU,
+ * held until the process ends and found at index build time.  Limits:
+ * n_q <= FT_NOALLOC_MAX_QUERIES, total query support <= FT_NOALLOC_MAX_ITEMS,
+ * n_q * n_cand <= FT_NOALLOC_MAX_PAIRS, n_cand <= 4096; larger inputs return
+ * FT_ERANGE before any device work.  The index's device must be current.
+ * Every call on a GPU shares that GPU's array: calls that overlap on one
+ * GPU (from several host threads, or on several streams without ordering)
+ * race and must be serialised by the caller.  The call synchronises the
+ * stream to read validation results, so it cannot be captured in a graph.
+ * ---------------------------------------------------------------------- */
+#define FT_NOALLOC_MAX_QUERIES 65536
+#define FT_NOALLOC_MAX_ITEMS 262144
+#define FT_NOALLOC_MAX_PAIRS 1048576
+ft_status ft_flowtree_knn_noalloc(ft_index* index, const int64_t* q_off, const uint32_t* q_id,
+                                  const uint32_t* q_mass, int64_t n_q, const int64_t* cand,
+                                  int32_t n_cand, int32_t k, float* out_cost, int64_t* out_doc,
+                                  void* stream);
+
+/* ------------------------------------------------------------------------
  * ft_flowtree_cost_grad -- Flowtree cost of explicit (query, doc) pairs and
  * its gradient with the tree and the flow pattern held fixed.
  *

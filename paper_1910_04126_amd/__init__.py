@@ -13,7 +13,7 @@ import os
 
 import torch
 
-__all__ = ["Index", "build_tree", "quadtree_knn", "flowtree_knn", "flowtree_cost_grad",
+__all__ = ["Index", "build_tree", "quadtree_knn", "flowtree_knn", "flowtree_knn_noalloc", "flowtree_cost_grad",
            "flowtree_flows", "quadtree_pairs", "FtError", "FT_PLAIN", "FT_BATCHED",
            "FT_FWD", "FT_BWD", "lib_path", "load"]
 
@@ -53,6 +53,7 @@ def load():
         "ft_export_tree": ([p, p, p, p, p], ctypes.c_int),
         "ft_quadtree_knn": ([p, p, p, p, i64, p, i32, i32, p, p, p], ctypes.c_int),
         "ft_flowtree_knn": ([p, p, p, p, i64, p, i32, i32, i32, p, p, p], ctypes.c_int),
+        "ft_flowtree_knn_noalloc": ([p, p, p, p, i64, p, i32, i32, p, p, p], ctypes.c_int),
         "ft_flowtree_cost_grad": ([p, p, p, p, p, i64, p, p, i64, i32, p, p, p, p, p, p], ctypes.c_int),
         "ft_flowtree_flows": ([p, p, p, p, i64, p, p, i64, p, p, p, p, p, p, p], ctypes.c_int),
         "ft_quadtree_pairs": ([p, p, p, p, i64, p, p, i64, p, p], ctypes.c_int),
@@ -205,6 +206,24 @@ def flowtree_knn(index: Index, q_off, q_id, q_mass, k: int, cand=None, mode: int
     docs = torch.empty((n_q, k), dtype=torch.int64, device=dev)
     _check(load().ft_flowtree_knn(index.handle, _ptr(q_off), _ptr(q_id), _ptr(q_mass), n_q,
                                   _ptr(cand_t), n_cand, k, mode, _ptr(costs), _ptr(docs), _stream()))
+    return costs, docs
+
+
+def flowtree_knn_noalloc(index: Index, q_off, q_id, q_mass, k: int, cand, out=None):
+    """ft_flowtree_knn_noalloc -> (costs float32 [n_q, k], docs int64 [n_q, k]).
+    The library allocates nothing; pass out=(costs, docs) to reuse output
+    tensors as well."""
+    q_off, q_id, q_mass = _queries(q_off, q_id, q_mass)
+    n_q = q_off.numel() - 1
+    cand_t = _i64(cand)
+    n_cand = cand_t.shape[-1]
+    if out is None:
+        costs = torch.empty((n_q, k), dtype=torch.float32, device=q_off.device)
+        docs = torch.empty((n_q, k), dtype=torch.int64, device=q_off.device)
+    else:
+        costs, docs = out
+    _check(load().ft_flowtree_knn_noalloc(index.handle, _ptr(q_off), _ptr(q_id), _ptr(q_mass), n_q,
+                                          _ptr(cand_t), n_cand, k, _ptr(costs), _ptr(docs), _stream()))
     return costs, docs
 
 

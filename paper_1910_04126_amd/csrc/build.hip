@@ -487,6 +487,20 @@ __global__ __launch_bounds__(64) void k_emb_fill(
   if (lane == 0) S[j] = Ssum;
 }
 
+void launch_check_offsets(const int64_t* off, int64_t n, uint32_t* status, hipStream_t s) {
+  k_check_offsets<<<(unsigned)ceil_div(n, 256), 256, 0, s>>>(off, n, status);
+  FT_HIP(hipGetLastError());
+}
+
+void launch_prep_sort(const ft_index* ix, const int64_t* off, const uint32_t* id, const uint32_t* mass, int64_t n,
+                      uint32_t* rank, uint32_t* mass_out, uint16_t* pos, uint8_t* lcp, int64_t* cnt,
+                      uint32_t* status, hipStream_t s) {
+  k_prep_sort<<<(unsigned)n, 64, 0, s>>>(off, id, mass, n, ix->inv.as<uint32_t>(), ix->st.as<uint8_t>(),
+                                        ix->leafd.as<uint8_t>(), ix->V, ix->B, ix->Q, rank, mass_out, pos, lcp, cnt,
+                                        status);
+  FT_HIP(hipGetLastError());
+}
+
 void prepare_dists(ft_index* ix, Dists& D, const int64_t* off, const uint32_t* id, const uint32_t* mass,
                    int64_t n, bool with_embedding, hipStream_t s, const char* what) {
   FT_REQUIRE(n >= 1, FT_EINVAL, std::string(what) + ": need at least one distribution");
@@ -589,6 +603,7 @@ extern "C" ft_status ft_build_tree(const float* X, int64_t V, int32_t d, const i
       ix->Q = Q;
       FT_HIP(hipGetDevice(&ix->device));
       FT_HIP(hipDeviceGetAttribute(&ix->n_cu, hipDeviceAttributeMultiprocessorCount, ix->device));
+      (void)noalloc_scratch(ix->device);  // set-up of the no-allocation entry point on this device
       FT_HIP(hipStreamCreateWithFlags(&ix->work, hipStreamNonBlocking));
       FT_HIP(hipEventCreateWithFlags(&ix->ev_a, hipEventDisableTiming));
       FT_HIP(hipEventCreateWithFlags(&ix->ev_b, hipEventDisableTiming));

@@ -180,6 +180,16 @@ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 void prepare_dists(ft_index* ix, Dists& D, const int64_t* off, const uint32_t* id,
                    const uint32_t* mass, int64_t n, bool with_embedding, hipStream_t s,
                    const char* what);
+// Launch-only pieces of prepare_dists over caller-provided memory: offsets
+// validation (status[0] flags, status[1] largest support) and the
+// per-distribution sort into Morton ranks (status[0] flags).
+void launch_check_offsets(const int64_t* off, int64_t n, uint32_t* status, hipStream_t s);
+void launch_prep_sort(const ft_index* ix, const int64_t* off, const uint32_t* id, const uint32_t* mass, int64_t n,
+                      uint32_t* rank, uint32_t* mass_out, uint16_t* pos, uint8_t* lcp, int64_t* cnt,
+                      uint32_t* status, hipStream_t s);
+// Device address of the no-allocation entry point's scratch array on a
+// device (looked up once per device; that device must be current).
+void* noalloc_scratch(int device);
 int64_t scan_tmp_elems(int64_t n);
 void exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* tmp, hipStream_t s);
 uint32_t read_and_clear_status(ft_index* ix, hipStream_t s);

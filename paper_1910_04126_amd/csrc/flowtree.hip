@@ -9,6 +9,7 @@
 #include <cstdlib>
 #include <fstream>
 #include <functional>
+#include <mutex>
 #include <sstream>
 #include <type_traits>
 #include <vector>
@@ -89,6 +90,27 @@ __global__ __launch_bounds__(64 * W, (flow_min_waves<C, W>())) void k_flow_persi
     const int64_t i1 = min(end, i0 + chunk);
     for (int64_t i = i0; i < i1; ++i) flow_one<C, W, G>(L, a, list[i]);
   }
+}
+
+// All pairs of one size class out of a flat list of n_pairs (query p /
+// n_cols, doc cand[p]): workgroups stride over the list and skip the pairs
+// of other classes (the no-allocation path has no room for class lists).
+template <int C, int W, int G>
+__global__ __launch_bounds__(64 * W, (flow_min_waves<C, W>())) void k_flow_class_stride(PairArgs a, int64_t n_pairs,
+                                                                                    int cls) {
+  __shared__ FlowLds<C, W> L;
+  for (int64_t p = blockIdx.x; p < n_pairs; p += gridDim.x) {
+    const int64_t q = p / a.n_cols;
+    const int64_t doc = a.cand[p];
+    const int n = (int)(a.q_off[q + 1] - a.q_off[q]) + (int)(a.d_off[doc + 1] - a.d_off[doc]);
+    if (class_for_dev(n) == cls) flow_one<C, W, G>(L, a, p);
+  }
+}
+
+// status[0] |= ERR_ID_RANGE unless every v[i] lies in [0, bound).
+__global__ void k_check_range(const int64_t* __restrict__ v, int64_t n, int64_t bound, uint32_t* __restrict__ status) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && (v[i] < 0 || v[i] >= bound)) atomicOr(status, ERR_ID_RANGE);
 }
 
 __global__ void k_fill_u32(uint32_t* p, int n, uint32_t v) {
@@ -451,3 +473,139 @@ extern "C" ft_status ft_last_batched_stats(const ft_index* ix, double* ms, char*
   });
 }
 
+
+// ---------------------------------------------------- no allocation --
+//
+// ft_flowtree_knn_noalloc keeps everything beyond its inputs and outputs in
+// `scratch`, one array per GPU (each device holds its own copy at its own
+// address).  In host code `scratch` only names the symbol: its device
+// address comes from hipGetSymbolAddress, once per device, and only that
+// address is handed to kernels and copies.
+
+namespace {
+
+constexpr int64_t na_align(int64_t x) { return (x + 255) & ~int64_t(255); }
+
+constexpr int64_t NA_STATUS = 0;                                                      // u32 [64]
+constexpr int64_t NA_OFF = na_align(NA_STATUS + 64 * 4);                              // int64 [MAX_Q + 1]
+constexpr int64_t NA_RANK = na_align(NA_OFF + (FT_NOALLOC_MAX_QUERIES + 1) * 8);      // u32 [MAX_ITEMS]
+constexpr int64_t NA_MASS = na_align(NA_RANK + (int64_t)FT_NOALLOC_MAX_ITEMS * 4);    // u32 [MAX_ITEMS]
+constexpr int64_t NA_POS = na_align(NA_MASS + (int64_t)FT_NOALLOC_MAX_ITEMS * 4);     // u16 [MAX_ITEMS]
+constexpr int64_t NA_LCP = na_align(NA_POS + (int64_t)FT_NOALLOC_MAX_ITEMS * 2);      // u8  [MAX_ITEMS]
+constexpr int64_t NA_CNT = na_align(NA_LCP + (int64_t)FT_NOALLOC_MAX_ITEMS);          // int64 [MAX_Q]
+constexpr int64_t NA_COST = na_align(NA_CNT + (int64_t)FT_NOALLOC_MAX_QUERIES * 8);   // f32 [MAX_PAIRS]
+constexpr int64_t NA_BYTES = na_align(NA_COST + (int64_t)FT_NOALLOC_MAX_PAIRS * 4);
+
+constexpr int NA_MAX_DEVICES = 64;
+std::mutex g_na_mu;
+void* g_na_ptr[NA_MAX_DEVICES] = {};
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[NA_BYTES];
+
+void* ft::noalloc_scratch(int device) {
+  std::lock_guard<std::mutex> lock(g_na_mu);
+  FT_REQUIRE(device >= 0 && device < NA_MAX_DEVICES, FT_EINVAL, "device ordinal out of range");
+  if (!g_na_ptr[device]) {
+    int cur = -1;
+    FT_HIP(hipGetDevice(&cur));
+    FT_REQUIRE(cur == device, FT_EINVAL, "the index's device must be current");
+    void* p = nullptr;
+    FT_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    FT_REQUIRE(p != nullptr, FT_EHIP, "no device address for the scratch array");
+    g_na_ptr[device] = p;
+  }
+  return g_na_ptr[device];
+}
+
+// Copies the status words of the scratch array to the host (synchronises s).
+static void na_read_status(const uint32_t* status, uint32_t* h, hipStream_t s) {
+  FT_HIP(hipMemcpyAsync(h, status, 8 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  FT_HIP(hipStreamSynchronize(s));
+}
+
+extern "C" ft_status ft_flowtree_knn_noalloc(ft_index* ix, const int64_t* q_off, const uint32_t* q_id,
+                                             const uint32_t* q_mass, int64_t n_q, const int64_t* cand, int32_t n_cand,
+                                             int32_t k, float* out_cost, int64_t* out_doc, void* stream) {
+  return guarded([&] {
+    FT_REQUIRE(ix && q_off && q_id && q_mass && cand && out_cost && out_doc, FT_EINVAL, "NULL argument");
+    FT_REQUIRE(n_q >= 1, FT_EINVAL, "queries: need at least one distribution");
+    FT_REQUIRE(n_cand >= 1 && n_cand <= 4096, FT_ERANGE, "n_cand must lie in [1, 4096]");
+    FT_REQUIRE(k >= 1 && k <= n_cand, FT_EINVAL, "k must lie in [1, number of candidates]");
+    FT_REQUIRE(n_q <= FT_NOALLOC_MAX_QUERIES, FT_ERANGE, "n_q exceeds FT_NOALLOC_MAX_QUERIES");
+    FT_REQUIRE(n_q * (int64_t)n_cand <= FT_NOALLOC_MAX_PAIRS, FT_ERANGE,
+               "n_q * n_cand exceeds FT_NOALLOC_MAX_PAIRS");
+    std::lock_guard<std::mutex> lock(ix->mu);
+    hipStream_t s = (hipStream_t)stream;
+    char* base = static_cast<char*>(noalloc_scratch(ix->device));
+    uint32_t* status = reinterpret_cast<uint32_t*>(base + NA_STATUS);
+    int64_t* off = reinterpret_cast<int64_t*>(base + NA_OFF);
+    uint32_t* rank = reinterpret_cast<uint32_t*>(base + NA_RANK);
+    uint32_t* mass = reinterpret_cast<uint32_t*>(base + NA_MASS);
+    uint16_t* pos = reinterpret_cast<uint16_t*>(base + NA_POS);
+    uint8_t* lcp = reinterpret_cast<uint8_t*>(base + NA_LCP);
+    int64_t* cnt = reinterpret_cast<int64_t*>(base + NA_CNT);
+    float* cost = reinterpret_cast<float*>(base + NA_COST);
+    uint32_t h[8];
+
+    // the previous call left its status words behind: clear them
+    k_fill_u32<<<1, 64, 0, s>>>(status, 64, 0u);
+    FT_HIP(hipGetLastError());
+    // query offsets: validated, and the total support bounded before any
+    // item is written
+    FT_HIP(hipMemcpyAsync(off, q_off, (n_q + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+    launch_check_offsets(off, n_q, status, s);
+    int64_t nnz = 0;
+    FT_HIP(hipMemcpyAsync(&nnz, off + n_q, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    na_read_status(status, h, s);
+    if (h[0] & ERR_SIZE) throw Error(FT_ERANGE, "queries: support larger than FT_MAX_SUPPORT");
+    if (h[0]) throw Error(FT_EINVAL, "queries:" + describe_flags(h[0]));
+    FT_REQUIRE(nnz <= FT_NOALLOC_MAX_ITEMS, FT_ERANGE, "total query support exceeds FT_NOALLOC_MAX_ITEMS");
+    const int max_q = (int)h[1];
+    const int top_cls = class_for(max_q + ix->docs.max_size);
+    FT_REQUIRE(top_cls >= 0, FT_ERANGE, "pair larger than 2048 items");
+    // queries sorted into Morton ranks; candidates in range
+    launch_prep_sort(ix, off, q_id, q_mass, n_q, rank, mass, pos, lcp, cnt, status, s);
+    const int64_t n_pairs = n_q * (int64_t)n_cand;
+    k_check_range<<<(unsigned)ceil_div(n_pairs, 256), 256, 0, s>>>(cand, n_pairs, ix->docs.n, status);
+    FT_HIP(hipGetLastError());
+    na_read_status(status, h, s);
+    if (h[0]) throw Error(FT_EINVAL, "queries or cand:" + describe_flags(h[0]));
+
+    PairArgs a;
+    a.q_off = off;
+    a.q_rank = rank;
+    a.q_mass = mass;
+    a.d_off = ix->docs.off.as<int64_t>();
+    a.d_rank = ix->docs.rank.as<uint32_t>();
+    a.d_mass = ix->docs.mass.as<uint32_t>();
+    a.cand = cand;
+    a.n_cols = n_cand;
+    a.st = ix->st.as<uint8_t>();
+    a.V = ix->V;
+    a.B = ix->B;
+    a.Q = ix->Q;
+    a.X = ix->Xm.as<float>();
+    a.stride = ix->dp;
+    a.status = status;
+    a.cost = cost;
+    const int G = lanes_for(ix->dp / 4);
+    for (int cls = 0; cls <= top_cls; ++cls) {
+      with_class(cls, [&](auto cc, auto ww) {
+        with_lanes(G, [&](auto gg) {
+          constexpr int C = decltype(cc)::value, W = decltype(ww)::value, GG = decltype(gg)::value;
+          int per_cu = 0;
+          FT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+              &per_cu, reinterpret_cast<const void*>(&k_flow_class_stride<C, W, GG>), 64 * W, 0));
+          const unsigned blocks = (unsigned)std::min<int64_t>(n_pairs, (int64_t)std::max(1, per_cu) * ix->n_cu);
+          k_flow_class_stride<C, W, GG><<<blocks, 64 * W, 0, s>>>(a, n_pairs, cls);
+        });
+      });
+      FT_HIP(hipGetLastError());
+    }
+    topk_rows(cost, n_q, n_cand, cand, k, out_cost, out_doc, s);
+    na_read_status(status, h, s);
+    FT_REQUIRE(h[0] == 0, FT_EHIP, "flowtree kernel reported:" + describe_flags(h[0]));
+  });
+}
