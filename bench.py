@@ -11,7 +11,7 @@ value = Flowtree pairs of the step / step time (the prune included).
 The plain one-launch-per-query Flowtree stage is timed on the same
 candidates afterwards and reported beside it.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload batched|text|image]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload batched|batched_v1m|text|image]
        [--no-cpu-baseline] [--no-plain]
        python bench.py --workload act [--act-cand C] [--act-iters I]   (the R-WMD / ACT stage after
                                                               Flowtree: Quadtree 1000 -> Flowtree C -> ACT-I top-20)
@@ -78,6 +78,11 @@ def workload(name):
                                                "mixture); 1000000 docs and 4096 queries, sizes 5..500 with "
                                                "P(m)~m^-1.1, Zipf(1.1) words; Quadtree prune to 1000 over all docs, "
                                                "batched Flowtree rerank to top-20")
+    if name == "batched_v1m":
+        return gen.make("batched", V=1_000_000), 1000, 20, (
+            "batched with V=1000000 ground points in R^300 (1.2 GB of coordinates, past the 256 MB "
+            "Infinity Cache); 1000000 docs and 4096 queries, sizes 5..500 with P(m)~m^-1.1, Zipf(1.1) "
+            "words; Quadtree prune to 1000 over all docs, batched Flowtree rerank to top-20")
     if name == "text":
         return gen.make("text"), 1000, 20, ("text-shaped: V=100000 d=300, 100000 docs and 1000 queries of 20..200 "
                                             "words; Quadtree prune to 1000, batched Flowtree rerank to top-20")
@@ -101,6 +106,9 @@ def main():
     ap.add_argument("--act-iters", type=int, default=1)
     ap.add_argument("--sk-iters", type=int, default=1)
     ap.add_argument("--trees", type=int, default=5)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="batched Flowtree on the default schedule (chunk 4, full occupancy) instead of timing "
+                         "ten schedules on the first call; for short profiled runs")
     args = ap.parse_args()
     if args.calibrate_copy:
         return calibrate_copy(args.calibrate_copy)
@@ -139,6 +147,8 @@ def main():
     torch.cuda.synchronize()
     info = ix.info()
     log("built index in %.1fs: %s" % (time.time() - t0, info))
+    if args.no_autotune:
+        ix.set_autotune(0)
     qo, qi, qm = T(ds.q_off), T(ds.q_id), T(ds.q_mass)
     n_q = ds.n_queries
 
@@ -210,6 +220,8 @@ def main():
                  "identical_output": same}
         log("plain: %.1f ms vs batched %.1f ms" % (pms, float(np.mean(stage_ft))))
 
+    copy_gbs = measure_copy_gbs()
+    log("device copy: %.0f GB/s" % copy_gbs)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(ds, prune, k, n_cols)
@@ -229,10 +241,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "queries": n_q, "docs": ds.n_docs, "V": ds.V, "d": ds.d,
                    "prune_k": prune, "k": k, "flowtree_pairs_per_step": ft_pairs},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.workload),
-                     "kernel": "k_flow_persistent (all size classes, one graph)",
-                     "kernel_ms": round(kms, 3), "algorithmic_bytes": alg_bytes},
+        "roofline": roofline_block(achieved, kms, alg_bytes, measured_traffic(args.workload), copy_gbs,
+                                   "k_flow_persistent (all size classes, one graph)"),
         "stages": {"quadtree_prune_ms": round(float(np.mean(stage_qt)), 3),
                    "quadtree_pairs_per_s": round(n_q * ds.n_docs / (float(np.mean(stage_qt)) * 1e-3), 1)
                    if prune else None,
@@ -244,6 +254,43 @@ def main():
         "index": info,
     }
     print(json.dumps(out), flush=True)
+
+
+def measure_copy_gbs(nbytes=1 << 31, reps=5):
+    """Read + write rate of a plain device-to-device copy of nbytes (best of
+    reps), the measured counterpart of the 8 TB/s HBM figure."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    b.copy_(a)
+    best = float("inf")
+    for _ in range(reps):
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / (best * 1e-3) / 1e9
+
+
+def roofline_block(achieved, kernel_ms, alg_bytes, traffic, copy_gbs, kernel):
+    """The roofline object of the bench line: algorithmic bytes per launch
+    over the kernel's live duration against the HBM peak, with the counted
+    HBM bytes (rocprofv3 FETCH_SIZE / WRITE_SIZE, when taken on these
+    sources) as a rate and a fraction of peak beside it, and the measured
+    copy rate."""
+    r = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kernel,
+         "kernel_ms": round(kernel_ms, 3), "algorithmic_bytes": alg_bytes,
+         "copy_measured_gbs": round(copy_gbs, 1)}
+    if traffic:
+        counted = traffic / (kernel_ms * 1e-3) / 1e9
+        r["counted_hbm_gbs"] = round(counted, 1)
+        r["counted_hbm_frac"] = round(counted / HBM_PEAK_GBS, 4)
+    return r
 
 
 RANDOM_MODEL_SETTINGS = (
@@ -289,9 +336,13 @@ def random_model_experiment(args):
         for N in Ns:
             rng = np.random.default_rng(1000003 * N + 97 * s + d)
             ok_qt = ok_ft = exact = 0
+            rnd_qt = rnd_ft = 0.0     # success with ties at the minimum broken uniformly at random
+            tie_qt = tie_ft = 0       # planted doc at the minimum together with another doc
             zero = torch.zeros(1, dtype=torch.int64, device=dev)
             planted_cost = torch.empty(1, dtype=torch.float32, device=dev)
             for rep in range(args.reps):
+                if rep and rep % 25 == 0:
+                    log("  N=%d s=%d: %d of %d repetitions" % (N, s, rep, args.reps))
                 ds = gen.random_model_swaps(rng, N, d, s, eps)
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
@@ -313,13 +364,36 @@ def random_model_experiment(args):
                 costs, kd, fd = costs.cpu().numpy()[0], kd.cpu().numpy()[0], fd.cpu().numpy()[0]
                 ok_qt += int(kd[0] == 0 and keys[0] < keys[1])
                 ok_ft += int(fd[0] == 0 and costs[0] < costs[1])
+                # every doc's value, for the tie rules: how many docs share
+                # the smallest value with the planted one
+                pq = torch.zeros(ds.n_docs, dtype=torch.int64, device=dev)
+                pd = torch.arange(ds.n_docs, dtype=torch.int64, device=dev)
+                allk = ft.quadtree_pairs(ix, *q, pq, pd).cpu().numpy().view(np.uint64)
+                allc = torch.empty(ds.n_docs, dtype=torch.float32, device=dev)
+                ft.flowtree_cost_grad(ix, Xd, *q, pq, pd, ft.FT_FWD, cost=allc)
+                allc = allc.cpu().numpy()
+                for vals, name in ((allk, "qt"), (allc, "ft")):
+                    at_min = vals == vals.min()
+                    if at_min[0]:
+                        share = 1.0 / at_min.sum()
+                        if name == "qt":
+                            rnd_qt += share
+                            tie_qt += int(at_min.sum() > 1)
+                        else:
+                            rnd_ft += share
+                            tie_ft += int(at_min.sum() > 1)
                 pairs += 2 * ds.n_docs
                 del ix
-            results.append({"d": d, "s": s, "eps": eps, "N": N, "docs": 1 + s * (N - s), "reps": args.reps,
-                             "quadtree_success": ok_qt / args.reps, "flowtree_success": ok_ft / args.reps,
-                             "flowtree_planted_exact": exact / args.reps})
-            log("random model d=%d s=%d eps=%.2f N=%d: quadtree %.2f flowtree %.2f (planted exact %.2f)" % (
-                d, s, eps, N, ok_qt / args.reps, ok_ft / args.reps, exact / args.reps))
+            R = args.reps
+            results.append({"d": d, "s": s, "eps": eps, "N": N, "docs": 1 + s * (N - s), "reps": R,
+                             "quadtree_success": ok_qt / R, "flowtree_success": ok_ft / R,
+                             "quadtree_success_random_ties": round(rnd_qt / R, 4),
+                             "flowtree_success_random_ties": round(rnd_ft / R, 4),
+                             "quadtree_tied_at_min": tie_qt / R, "flowtree_tied_at_min": tie_ft / R,
+                             "flowtree_planted_exact": exact / R})
+            log("random model d=%d s=%d eps=%.2f N=%d: strict quadtree %.2f flowtree %.2f; random ties "
+                "quadtree %.3f flowtree %.3f; tied at min quadtree %.2f flowtree %.2f (planted exact %.2f)" % (
+                    d, s, eps, N, ok_qt / R, ok_ft / R, rnd_qt / R, rnd_ft / R, tie_qt / R, tie_ft / R, exact / R))
     out = {"metric": "random-model planted nearest neighbour recovered (fraction of repetitions), "
                      "Quadtree vs Flowtree, as N grows",
            "unit": "fraction", "higher_is_better": True, "n_gpus": 1, "data": "synthetic",
@@ -685,40 +759,80 @@ def calibrate_copy(nbytes):
     print(json.dumps({"copy_bytes": nbytes, "copies": 5}), flush=True)
 
 
+def cpu_threads():
+    """Host threads for the all-cores oracle leg: the CPUs this process may
+    run on, capped by OMP_NUM_THREADS when it is set (the GPU machine gives a
+    one-GPU job 16)."""
+    n = len(os.sched_getaffinity(0))
+    cap = os.environ.get("OMP_NUM_THREADS")
+    if cap and cap.isdigit() and int(cap) > 0:
+        n = min(n, int(cap))
+    return max(1, n)
+
+
+def _oracle_pipeline(ds, prune, k, n_cols, threads, budget):
+    """Whole-pipeline queries of the CPU oracle (Quadtree on every doc,
+    top-`prune`, Flowtree on those, top-k; or Flowtree on every doc when
+    prune = 0), one query per thread at a time, each thread with its own
+    oracle tree, until `budget` seconds have passed.  Returns (queries done,
+    seconds)."""
+    import itertools
+    import threading
+
+    import oracle
+    trees = [oracle.Tree(ds.X, ds.shift, ds.B) for _ in range(threads)]
+    docs = np.arange(ds.n_docs)
+    next_q = itertools.count()
+    lock = threading.Lock()
+    done = [0] * threads
+    t_start = time.perf_counter()
+
+    def worker(i):
+        Tr = trees[i]
+        while time.perf_counter() - t_start < budget:
+            with lock:
+                q = next(next_q)
+            if q >= ds.n_queries:
+                return
+            if prune:
+                U = Tr.quadtree_pairs(ds.q_off, ds.q_id, ds.q_mass, ds.doc_off, ds.doc_id, ds.doc_mass,
+                                      np.full(ds.n_docs, q), docs, ds.Q)
+                _, cand = oracle.topk(U, docs, prune)
+            else:
+                cand = docs
+            F = Tr.flowtree_pairs(ds.q_off, ds.q_id, ds.q_mass, ds.doc_off, ds.doc_id, ds.doc_mass,
+                                  np.full(len(cand), q), cand, ds.Q)
+            oracle.topk(F, cand, k)
+            done[i] += 1
+
+    ths = [threading.Thread(target=worker, args=(i,)) for i in range(threads)]
+    for th in ths:
+        th.start()
+    for th in ths:
+        th.join()
+    return sum(done), time.perf_counter() - t_start
+
+
 def cpu_baseline(ds, prune, k, n_cols):
     """The CPU oracle on a bounded sample of the same workload: the full
-    pipeline for a few queries (Quadtree against every doc, top-`prune`,
-    Flowtree on those candidates, top-k), single-threaded; scaled to
-    Flowtree pairs per second of that pipeline."""
-    import oracle
-    t0 = time.time()
-    Tr = oracle.Tree(ds.X, ds.shift, ds.B)
-    log("cpu baseline: oracle tree built in %.1fs" % (time.time() - t0))
-    docs = np.arange(ds.n_docs)
-    budget = 20.0
-    done = 0
-    t_start = time.perf_counter()
-    for q in range(ds.n_queries):
-        pq = np.full(ds.n_docs if prune else n_cols, q)
-        if prune:
-            U = Tr.quadtree_pairs(ds.q_off, ds.q_id, ds.q_mass, ds.doc_off, ds.doc_id, ds.doc_mass, pq, docs, ds.Q)
-            _, cand = oracle.topk(U, docs, prune)
-        else:
-            cand = docs
-        F = Tr.flowtree_pairs(ds.q_off, ds.q_id, ds.q_mass, ds.doc_off, ds.doc_id, ds.doc_mass,
-                              np.full(len(cand), q), cand, ds.Q)
-        oracle.topk(F, cand, k)
-        done += 1
-        if time.perf_counter() - t_start > budget:
-            break
-    el = time.perf_counter() - t_start
-    log("cpu baseline: %d queries in %.1fs" % (done, el))
-    return {"value": round(done * n_cols / el, 2), "unit": "pairs/s", "cores": 1, "kind": "oracle",
-            "sample": "%d of %d queries through the whole pipeline (%s), single-threaded C oracle; "
-                      "pairs/s counts the Flowtree pairs of those queries" %
-                      (done, ds.n_queries, ("Quadtree on all %d docs, top-%d, Flowtree, top-%d" %
-                                            (ds.n_docs, prune, k)) if prune else
-                      ("Flowtree on all %d docs, top-%d" % (ds.n_docs, k)))}
+    pipeline for whole queries (Quadtree against every doc, top-`prune`,
+    Flowtree on those candidates, top-k), once on one thread (as the paper
+    times its implementation) and once on all host cores with one query per
+    thread; scaled to Flowtree pairs per second of that pipeline.  The main
+    value is the all-cores leg."""
+    what = (("Quadtree on all %d docs, top-%d, Flowtree, top-%d" % (ds.n_docs, prune, k)) if prune else
+            ("Flowtree on all %d docs, top-%d" % (ds.n_docs, k)))
+    n1, t1 = _oracle_pipeline(ds, prune, k, n_cols, 1, 15.0)
+    log("cpu baseline: 1 thread, %d queries in %.1fs" % (n1, t1))
+    nt = cpu_threads()
+    nn, tn = _oracle_pipeline(ds, prune, k, n_cols, nt, 15.0)
+    log("cpu baseline: %d threads, %d queries in %.1fs" % (nt, nn, tn))
+    return {"value": round(nn * n_cols / tn, 2), "unit": "pairs/s", "cores": nt, "kind": "oracle",
+            "sample": "%d of %d queries through the whole pipeline (%s), C oracle on %d host threads, one "
+                      "query per thread; pairs/s counts the Flowtree pairs of those queries" %
+                      (nn, ds.n_queries, what, nt),
+            "single_thread": {"value": round(n1 * n_cols / t1, 2), "unit": "pairs/s", "cores": 1,
+                              "sample": "%d queries, same pipeline, one thread" % n1}}
 
 
 if __name__ == "__main__":

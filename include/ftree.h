@@ -187,7 +187,11 @@ ft_status ft_flowtree_knn_noalloc(ft_index* index, const int64_t* q_off, const u
  *             carries the unmatched mass of the item it used up (the dataset
  *             item when both were used up), which makes the cost linear in
  *             w; the gradient in X is eta * (x - y) / ||x - y|| per match
- *             (0 for coincident points).
+ *             (0 for coincident points).  The gradients are reproducible to
+ *             the bit: dX is summed in 64-bit fixed point (unit 2^-40 of the
+ *             largest |grad_out|, fewer fraction bits past 2^21 pairs), the
+ *             weight gradients over each query's and each doc's pairs in pair
+ *             order.  A non-finite grad_out gives FT_EINVAL.
  * ---------------------------------------------------------------------- */
 ft_status ft_flowtree_cost_grad(ft_index* index, const float* X, const int64_t* q_off,
                                 const uint32_t* q_id, const uint32_t* q_mass, int64_t n_q,

@@ -445,7 +445,7 @@ static int cmp_rank(const void* a, const void* b) {
   return (x->rank > y->rank) - (x->rank < y->rank);
 }
 
-static const otree* g_sort_tree; /* qsort has no context argument */
+static _Thread_local const otree* g_sort_tree; /* qsort has no context argument; one per thread */
 static int cmp_node_depth(const void* a, const void* b) {
   int64_t x = *(const int64_t*)a, y = *(const int64_t*)b;
   int32_t dx = g_sort_tree->depth[x], dy = g_sort_tree->depth[y];

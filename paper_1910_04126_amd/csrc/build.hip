@@ -65,6 +65,7 @@ std::string describe_flags(uint32_t f) {
   if (f & ERR_SIZE) s += " support larger than FT_MAX_SUPPORT;";
   if (f & ERR_EMPTY) s += " empty distribution or bad offsets;";
   if (f & ERR_FLOW) s += " internal flow inconsistency;";
+  if (f & ERR_NONFINITE) s += " non-finite value;";
   return s;
 }
 
@@ -563,6 +564,7 @@ extern "C" void ft_free(ft_index* ix) {
   ix->graphs.reset();
   for (DevBuf* b : {&ix->post, &ix->post_dir, &ix->post_cbase, &ix->Xm, &ix->Xn, &ix->perm, &ix->inv, &ix->st, &ix->leafd, &ix->anc, &ix->status, &ix->ws_keys,
                     &ix->ws_cost, &ix->ws_tiles, &ix->ws_lists, &ix->ws_counts, &ix->ws_misc, &ix->ws_sel, &ix->ws_rerank,
+                    &ix->ws_gx64, &ix->ws_adj, &ix->ws_glist,
                     &ix->fwd_id, &ix->fwd_eta, &ix->fwd_key, &ix->fwd_bind, &ix->fwd_cnt, &ix->fwd_base, &ix->fwd_sig})
     b->release();
   ix->docs.release();

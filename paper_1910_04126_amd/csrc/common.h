@@ -75,6 +75,7 @@ enum : uint32_t {
   ERR_SIZE = 16u,
   ERR_EMPTY = 32u,
   ERR_FLOW = 64u,  // internal consistency of the greedy (must never fire)
+  ERR_NONFINITE = 128u,  // a non-finite input value
 };
 std::string describe_flags(uint32_t f);
 
@@ -141,6 +142,7 @@ struct ft_index {
   // per-call workspaces
   ft::Dists qry;
   ft::DevBuf ws_keys, ws_cost, ws_tiles, ws_lists, ws_counts, ws_misc, ws_sel, ws_rerank;
+  ft::DevBuf ws_gx64, ws_adj, ws_glist;  // backward: fixed-point dX, per-pair weight adjoints, pair lists
   ft::DevBuf fwd_id, fwd_eta, fwd_key, fwd_bind, fwd_cnt, fwd_base;  // saved flows (FT_FWD)
   int64_t fwd_pairs = 0, fwd_cap = 0;
   ft::DevBuf fwd_sig;          // copies of the FT_FWD query CSR and pairs

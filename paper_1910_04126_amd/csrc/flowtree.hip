@@ -118,6 +118,22 @@ __global__ void k_fill_u32(uint32_t* p, int n, uint32_t v) {
   if (i < n) p[i] = v;
 }
 
+// Per query: the largest support among its candidates (the plain
+// schedule's workgroup shape).
+__global__ __launch_bounds__(256) void k_cand_max_size(PairArgs a, int32_t* __restrict__ out) {
+  __shared__ int32_t wmax[4];
+  const int64_t q = blockIdx.x;
+  int m = 0;
+  for (int64_t c = threadIdx.x; c < a.n_cols; c += blockDim.x) {
+    const int64_t doc = a.cand ? a.cand[q * a.n_cols + c] : c;
+    m = max(m, (int)(a.d_off[doc + 1] - a.d_off[doc]));
+  }
+  m = wave_max(m);
+  if (lane_id() == 0) wmax[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) out[q] = max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3]));
+}
+
 // Per query: count candidate pairs of each size class.
 __global__ __launch_bounds__(256) void k_bucket_count(PairArgs a, int64_t n_q, int64_t* __restrict__ counts) {
   __shared__ int64_t cnt[N_CLASSES];
@@ -306,13 +322,21 @@ static void set_blocks(ft_index* ix, BatchedPlan& P, int occupancy_percent) {
 
 using namespace ft;
 
+// Plain schedule: one launch per query, its workgroup shape sized by the
+// query's largest pair (the query's support plus its largest candidate,
+// found on the device first).
 static void flowtree_plain(ft_index* ix, const PairArgs& a, int64_t n_q, hipStream_t s) {
   std::vector<int64_t> qoff(n_q + 1);
+  std::vector<int32_t> dmax(n_q);
+  int32_t* dev_max = (int32_t*)ix->ws_misc.ensure(n_q * sizeof(int32_t));
+  k_cand_max_size<<<(unsigned)n_q, 256, 0, s>>>(a, dev_max);
+  FT_HIP(hipGetLastError());
   FT_HIP(hipMemcpyAsync(qoff.data(), a.q_off, (n_q + 1) * 8, hipMemcpyDeviceToHost, s));
+  FT_HIP(hipMemcpyAsync(dmax.data(), dev_max, n_q * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   FT_HIP(hipStreamSynchronize(s));
   const int G = lanes_for(ix->dp / 4);
   for (int64_t q = 0; q < n_q; ++q) {
-    const int cls = class_for((int)(qoff[q + 1] - qoff[q]) + ix->docs.max_size);
+    const int cls = class_for((int)(qoff[q + 1] - qoff[q]) + dmax[q]);
     FT_REQUIRE(cls >= 0, FT_ERANGE, "pair larger than 2048 items");
     launch_plain(cls, G, a, q, s);
   }

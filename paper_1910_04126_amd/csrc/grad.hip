@@ -17,6 +17,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
+#include <utility>
 #include <vector>
 
 #include "common.h"
@@ -119,8 +121,8 @@ __global__ __launch_bounds__(BWD_THREADS) void k_flow_bwd(
     const uint64_t* __restrict__ fkey, const uint8_t* __restrict__ fbind, const int64_t* __restrict__ q_off,
     const uint32_t* __restrict__ q_rank, const uint16_t* __restrict__ q_pos, const int64_t* __restrict__ d_off,
     const uint32_t* __restrict__ d_rank, const uint16_t* __restrict__ d_pos, const uint32_t* __restrict__ perm,
-    const float* __restrict__ X, int d, int Q, const float* __restrict__ grad_out, float* __restrict__ gX,
-    float* __restrict__ gq, float* __restrict__ gd) {
+    const float* __restrict__ X, int d, int Q, const float* __restrict__ grad_out,
+    const double* __restrict__ unit, unsigned long long* __restrict__ gx64, double* __restrict__ adj) {
   constexpr int N = 64 * C;
   __shared__ uint64_t skey[N];
   __shared__ uint16_t sidx[N];
@@ -173,8 +175,8 @@ __global__ __launch_bounds__(BWD_THREADS) void k_flow_bwd(
     float dd = 0.0f;
     const float* xd = nullptr;
     const float* xq = nullptr;
-    float* gxd = nullptr;
-    float* gxq = nullptr;
+    unsigned long long* gxd = nullptr;
+    unsigned long long* gxq = nullptr;
     uint32_t eta = 0;
     if (r < E) {
       const int e = sidx[r];
@@ -184,8 +186,8 @@ __global__ __launch_bounds__(BWD_THREADS) void k_flow_bwd(
       if (rowd != rowq) {
         xd = X + rowd * d;
         xq = X + rowq * d;
-        gxd = gX ? gX + rowd * d : nullptr;
-        gxq = gX ? gX + rowq * d : nullptr;
+        gxd = gx64 ? gx64 + rowd * d : nullptr;
+        gxq = gx64 ? gx64 + rowq * d : nullptr;
         if (VEC == 4) {
           for (int i = sub; i < d / 4; i += G) {
             const float4 a4 = reinterpret_cast<const float4*>(xd)[i], b4 = reinterpret_cast<const float4*>(xq)[i];
@@ -211,11 +213,14 @@ __global__ __launch_bounds__(BWD_THREADS) void k_flow_bwd(
       skey[r] = ((uint64_t)fbind[b0 + e] << 32) | fid[b0 + e];
     }
     if (r < E && xd && D > 0.0f && gxd) {
+      // fixed point in units of unit[0] (a power of two): integer sums do not
+      // depend on the order of the additions, so dX is reproducible
       const float coef = (float)((double)g * (double)eta * wscale / (double)D);
+      const double inv = unit[1];
       for (int i = sub; i < d; i += G) {
-        const float diff = (xd[i] - xq[i]) * coef;
-        atomicAdd(gxd + i, diff);
-        atomicAdd(gxq + i, -diff);
+        const long long v = __double2ll_rn((double)((xd[i] - xq[i]) * coef) * inv);
+        atomicAdd(gxd + i, (unsigned long long)v);
+        atomicAdd(gxq + i, (unsigned long long)(-v));
       }
     }
   }
@@ -232,10 +237,89 @@ __global__ __launch_bounds__(BWD_THREADS) void k_flow_bwd(
     }
   }
   __syncthreads();
-  for (int i = tid; i < nq; i += BWD_THREADS)
-    if (gq) atomicAdd(gq + qa + q_pos[qa + i], (float)((double)g * acc[i]));
-  for (int i = tid; i < nd; i += BWD_THREADS)
-    if (gd) atomicAdd(gd + da + d_pos[da + i], (float)((double)g * acc[nq + i]));
+  // the pair's weight adjoints, query items then doc items; summed over the
+  // pairs of each query and each doc in pair order afterwards
+  if (adj)
+    for (int i = tid; i < nq + nd; i += BWD_THREADS) adj[b0 + i] = (double)g * acc[i];
+}
+
+// The fixed-point unit of dX: with G = max |grad_out| < 2^e and F fraction
+// bits, unit = 2^(e - F).  A match adds at most G * eta / 2^Q to an entry in
+// magnitude, and a pair's eta sum to 2^Q, so an entry's sum stays below
+// n_pairs * 2^F units (the host picks F accordingly).  Non-finite grad_out
+// is reported.
+__global__ __launch_bounds__(256) void k_grad_unit(const float* __restrict__ g, int64_t n, int frac_bits,
+                                                   double* __restrict__ unit, uint32_t* __restrict__ status) {
+  __shared__ float wmax[4];
+  float m = 0.0f;
+  bool bad = false;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const float v = fabsf(g[i]);
+    if (!(v <= 3.4e38f)) bad = true;
+    else m = fmaxf(m, v);
+  }
+  m = wave_max(m);
+  if (__ballot(bad) && lane_id() == 0) atomicOr(status, ERR_NONFINITE);
+  if (lane_id() == 0) wmax[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    m = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
+    const int e = m > 0.0f ? ilogbf(m) + 1 : 0;
+    unit[0] = ldexp(1.0, e - frac_bits);
+    unit[1] = ldexp(1.0, frac_bits - e);
+  }
+}
+
+// gX += fixed-point sums (entries no match touched are left alone).
+__global__ void k_grad_x_finish(const unsigned long long* __restrict__ gx64, int64_t n, const double* __restrict__ unit,
+                                float* __restrict__ gX) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && gx64[i]) gX[i] += (float)((double)(long long)gx64[i] * unit[0]);
+}
+
+__global__ void k_zero_u64(unsigned long long* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+// Query weight gradients: one wavefront per query, its pairs in increasing
+// pair order (list[lo[q]..lo[q+1])), each item's adjoints summed in that
+// order.
+__global__ __launch_bounds__(64) void k_grad_w_query(const int64_t* __restrict__ lo, const int64_t* __restrict__ list,
+                                                     const int64_t* __restrict__ base, const double* __restrict__ adj,
+                                                     const int64_t* __restrict__ q_off,
+                                                     const uint16_t* __restrict__ q_pos, float* __restrict__ gq) {
+  const int64_t q = blockIdx.x;
+  const int64_t qa = q_off[q];
+  const int nq = (int)(q_off[q + 1] - qa);
+  for (int i = threadIdx.x; i < nq; i += 64) {
+    double s = 0.0;
+    for (int64_t k = lo[q]; k < lo[q + 1]; ++k) s += adj[base[list[k]] + i];
+    if (lo[q + 1] > lo[q]) gq[qa + q_pos[qa + i]] += (float)s;
+  }
+}
+
+// Doc weight gradients: one wavefront per distinct doc of the pairs
+// (docs[j], its pairs list[lo[j]..lo[j+1]) in increasing pair order); a doc
+// item's slot in its pair follows the query's items.
+__global__ __launch_bounds__(64) void k_grad_w_doc(const int64_t* __restrict__ docs, const int64_t* __restrict__ lo,
+                                                   const int64_t* __restrict__ list, const int64_t* __restrict__ base,
+                                                   const double* __restrict__ adj, const int64_t* __restrict__ pair_q,
+                                                   const int64_t* __restrict__ q_off, const int64_t* __restrict__ d_off,
+                                                   const uint16_t* __restrict__ d_pos, float* __restrict__ gd) {
+  const int64_t j = blockIdx.x;
+  const int64_t doc = docs[j];
+  const int64_t da = d_off[doc];
+  const int nd = (int)(d_off[doc + 1] - da);
+  for (int i = threadIdx.x; i < nd; i += 64) {
+    double s = 0.0;
+    for (int64_t k = lo[j]; k < lo[j + 1]; ++k) {
+      const int64_t p = list[k];
+      const int64_t nq = q_off[pair_q[p] + 1] - q_off[pair_q[p]];
+      s += adj[base[p] + nq + i];
+    }
+    gd[da + d_pos[da + i]] += (float)s;
+  }
 }
 
 // Copies of the FT_FWD arguments, compared element by element in FT_BWD.
@@ -445,12 +529,83 @@ extern "C" ft_status ft_flowtree_cost_grad(ft_index* ix, const float* X, const i
     const int cls = class_for(ix->qry.max_size + ix->docs.max_size);
     const int G = lanes_for((ix->d + 3) / 4);
     const int VEC = (ix->d % 4 == 0 && ((uintptr_t)X & 15) == 0) ? 4 : 1;
+    // each query's and each doc's pairs in increasing pair order, for the
+    // weight gradients (made before any buffer below is sized)
+    const bool want_w = grad_qmass || grad_dmass;
+    std::vector<int64_t> qlo, qlist, ddocs, dlo, dlist;
+    if (want_w) {
+      std::vector<int64_t> hq(n_pairs), hd(n_pairs);
+      FT_HIP(hipMemcpyAsync(hq.data(), pair_q, n_pairs * 8, hipMemcpyDeviceToHost, s));
+      FT_HIP(hipMemcpyAsync(hd.data(), pair_d, n_pairs * 8, hipMemcpyDeviceToHost, s));
+      FT_HIP(hipStreamSynchronize(s));
+      qlo.assign(n_q + 1, 0);
+      qlist.resize(n_pairs);
+      for (int64_t p = 0; p < n_pairs; ++p) ++qlo[hq[p] + 1];
+      for (int64_t q = 0; q < n_q; ++q) qlo[q + 1] += qlo[q];
+      std::vector<int64_t> at(qlo.begin(), qlo.end() - 1);
+      for (int64_t p = 0; p < n_pairs; ++p) qlist[at[hq[p]]++] = p;
+      std::vector<std::pair<int64_t, int64_t>> dp(n_pairs);
+      for (int64_t p = 0; p < n_pairs; ++p) dp[p] = {hd[p], p};
+      std::sort(dp.begin(), dp.end());
+      dlist.resize(n_pairs);
+      for (int64_t k = 0; k < n_pairs; ++k) {
+        if (k == 0 || dp[k].first != dp[k - 1].first) {
+          ddocs.push_back(dp[k].first);
+          dlo.push_back(k);
+        }
+        dlist[k] = dp[k].second;
+      }
+      dlo.push_back(n_pairs);
+    }
+    const int64_t nu = (int64_t)ddocs.size();
+    // one buffer: the fixed-point unit (and its inverse), then the lists
+    int64_t* g = (int64_t*)ix->ws_glist.ensure((8 + (want_w ? (n_q + 1) + 2 * n_pairs + 2 * nu + 1 : 0)) * 8);
+    double* unit = reinterpret_cast<double*>(g);
+    unsigned long long* gx64 = nullptr;
+    const int64_t nx = ix->V * (int64_t)ix->d;
+    if (grad_X) gx64 = (unsigned long long*)ix->ws_gx64.ensure(nx * 8);
+    double* adj = want_w ? (double*)ix->ws_adj.ensure(std::max<int64_t>(ix->fwd_cap, 1) * 8) : nullptr;
+    // dX in fixed point: F fraction bits keep n_pairs * 2^F below 2^62
+    int frac = 40;
+    while (frac > 8 && (double)n_pairs * std::ldexp(1.0, frac) >= std::ldexp(1.0, 62)) --frac;
+    k_grad_unit<<<1, 256, 0, s>>>(grad_out, n_pairs, frac, unit, ix->status.as<uint32_t>());
+    FT_HIP(hipGetLastError());
+    if (read_and_clear_status(ix, s)) throw Error(FT_EINVAL, "grad_out must be finite");
+    if (gx64) {
+      k_zero_u64<<<(unsigned)ceil_div(nx, 256), 256, 0, s>>>(gx64, nx);
+      FT_HIP(hipGetLastError());
+    }
     FT_DISPATCH_CG(k_flow_bwd, cls, G, VEC, dim3((unsigned)n_pairs), BWD_THREADS, s, pair_q, pair_d, ix->fwd_base.as<int64_t>(),
                    ix->fwd_cnt.as<int32_t>(), ix->fwd_id.as<uint32_t>(), ix->fwd_eta.as<uint32_t>(),
                    ix->fwd_key.as<uint64_t>(), ix->fwd_bind.as<uint8_t>(), ix->qry.off.as<int64_t>(),
                    ix->qry.rank.as<uint32_t>(), ix->qry.pos.as<uint16_t>(), ix->docs.off.as<int64_t>(),
                    ix->docs.rank.as<uint32_t>(), ix->docs.pos.as<uint16_t>(), ix->perm.as<uint32_t>(), X, ix->d,
-                   ix->Q, grad_out, grad_X, grad_qmass, grad_dmass);
+                   ix->Q, grad_out, unit, gx64, adj);
     FT_HIP(hipGetLastError());
+    if (gx64) {
+      k_grad_x_finish<<<(unsigned)ceil_div(nx, 256), 256, 0, s>>>(gx64, nx, unit, grad_X);
+      FT_HIP(hipGetLastError());
+    }
+    if (!want_w) return;
+    int64_t* d_qlo = g + 8;
+    int64_t* d_qlist = d_qlo + (n_q + 1);
+    int64_t* d_docs = d_qlist + n_pairs;
+    int64_t* d_dlo = d_docs + nu;
+    int64_t* d_dlist = d_dlo + (nu + 1);
+    FT_HIP(hipMemcpyAsync(d_qlo, qlo.data(), (n_q + 1) * 8, hipMemcpyHostToDevice, s));
+    FT_HIP(hipMemcpyAsync(d_qlist, qlist.data(), n_pairs * 8, hipMemcpyHostToDevice, s));
+    FT_HIP(hipMemcpyAsync(d_docs, ddocs.data(), nu * 8, hipMemcpyHostToDevice, s));
+    FT_HIP(hipMemcpyAsync(d_dlo, dlo.data(), (nu + 1) * 8, hipMemcpyHostToDevice, s));
+    FT_HIP(hipMemcpyAsync(d_dlist, dlist.data(), n_pairs * 8, hipMemcpyHostToDevice, s));
+    if (grad_qmass)
+      k_grad_w_query<<<(unsigned)n_q, 64, 0, s>>>(d_qlo, d_qlist, ix->fwd_base.as<int64_t>(), adj,
+                                                  ix->qry.off.as<int64_t>(), ix->qry.pos.as<uint16_t>(), grad_qmass);
+    if (grad_dmass)
+      k_grad_w_doc<<<(unsigned)nu, 64, 0, s>>>(d_docs, d_dlo, d_dlist, ix->fwd_base.as<int64_t>(), adj, pair_q,
+                                               ix->qry.off.as<int64_t>(), ix->docs.off.as<int64_t>(),
+                                               ix->docs.pos.as<uint16_t>(), grad_dmass);
+    FT_HIP(hipGetLastError());
+    // the host lists must outlive the copies
+    FT_HIP(hipStreamSynchronize(s));
   });
 }

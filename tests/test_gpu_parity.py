@@ -420,6 +420,40 @@ def test_cost_grad_size_classes(ft, hi, d):
     check_cost_grad(ft, ds, pq, pd, 0.25, 2.0)
 
 
+def test_cost_grad_deterministic(ft):
+    """Two backward calls over pairs that share queries and docs (so several
+    pairs add into the same rows of dX and the same weights) give the same
+    gradients to the bit, and they match the oracle; a non-finite grad_out
+    is rejected."""
+    say("cost_grad: bit-identical gradients across calls, shared rows")
+    ds = gen.make("grad", V=3000, n_pairs=16)
+    rng = np.random.default_rng(41)
+    pq = rng.integers(0, 4, 64).astype(np.int64)
+    pd = rng.integers(0, 6, 64).astype(np.int64)
+    ix = build_index(ft, ds)
+    X = t(ds.X)
+    qo, qi, qm = queries(ds)
+    cost = torch.empty(len(pq), dtype=torch.float32, device=X.device)
+    ft.flowtree_cost_grad(ix, X, qo, qi, qm, t(pq), t(pd), ft.FT_FWD, cost=cost)
+    g_out = torch.from_numpy(rng.uniform(-2.0, 3.0, len(pq)).astype(np.float32)).to(X.device)
+    runs = []
+    for _ in range(2):
+        gX = torch.zeros_like(X)
+        gq = torch.zeros(len(ds.q_id), device=X.device)
+        gd = torch.zeros(len(ds.doc_id), device=X.device)
+        ft.flowtree_cost_grad(ix, X, qo, qi, qm, t(pq), t(pd), ft.FT_BWD, grad_out=g_out, grad_X=gX,
+                              grad_qmass=gq, grad_dmass=gd)
+        runs.append([v.cpu().numpy() for v in (gX, gq, gd)])
+    for a, b in zip(*runs):
+        assert np.array_equal(a.view(np.int32), b.view(np.int32))
+    want, wX, wq, wd = oracle_weighted_grad(ds, pq, pd, g_out.cpu().numpy().astype(np.float64))
+    assert_grads_close(*runs[0], wX, wq, wd)
+    bad = g_out.clone()
+    bad[7] = float("nan")
+    with pytest.raises(ft.FtError, match="finite"):
+        ft.flowtree_cost_grad(ix, X, qo, qi, qm, t(pq), t(pd), ft.FT_BWD, grad_out=bad, grad_X=torch.zeros_like(X))
+
+
 def test_autograd_function(ft):
     """FlowtreeCost through torch.autograd: the forward values and the
     gradients in X, q_w and d_w of sum_p g_p cost_p (g non-uniform) against
