@@ -153,7 +153,7 @@ def main():
     n_q = ds.n_queries
 
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-    stage_qt, stage_ft, kernel_ms = [], [], []
+    stage_qt, stage_ft, kernel_ms, sel_exact = [], [], [], []
 
     def step():
         ev[0].record()
@@ -179,6 +179,7 @@ def main():
         stage_qt.append(ev[0].elapsed_time(ev[1]))
         stage_ft.append(ev[1].elapsed_time(ev[2]))
         kernel_ms.append(ix.last_batched_stats()[0])
+        sel_exact.append(ix.last_select_exact_rows() if prune else 0)
         log("  step %d: quadtree %.1f ms, flowtree %.1f ms (persistent kernels %.1f ms)" % (
             i, stage_qt[-1], stage_ft[-1], kernel_ms[-1]))
     torch.cuda.synchronize()
@@ -244,6 +245,7 @@ def main():
         "roofline": roofline_block(achieved, kms, alg_bytes, measured_traffic(args.workload), copy_gbs,
                                    "k_flow_persistent (all size classes, one graph)"),
         "stages": {"quadtree_prune_ms": round(float(np.mean(stage_qt)), 3),
+                   "prune_select_exact_rows": int(np.max(sel_exact)) if sel_exact else 0,
                    "quadtree_pairs_per_s": round(n_q * ds.n_docs / (float(np.mean(stage_qt)) * 1e-3), 1)
                    if prune else None,
                    "flowtree_batched_ms": round(float(np.mean(stage_ft)), 3),

@@ -348,6 +348,13 @@ ft_status ft_set_autotune(ft_index* index, int32_t level);
 ft_status ft_last_batched_stats(const ft_index* index, double* ms_flowtree, char* schedule,
                                 int32_t schedule_len);
 
+/* Rows of the last ft_quadtree_knn call (more than 4096 candidates per row)
+ * whose one-pass select, which takes its threshold from a sample spread over
+ * the row, found too few or too many keys under it and ran the exact
+ * multi-pass select instead (the result is the same; the time is longer).
+ * Waits for the device. */
+ft_status ft_last_quadtree_stats(const ft_index* index, int64_t* select_exact_rows);
+
 /* Device time of the kernels of the last ft_act_knn, ft_sinkhorn_knn or
  * ft_exact_knn call (milliseconds, HIP events recorded on the caller's
  * stream around the kernel launches; the query preparation and the top-k

@@ -60,6 +60,7 @@ def load():
         "ft_act_knn": ([p, p, p, p, i64, p, i32, i32, i32, p, p, p], ctypes.c_int),
         "ft_act_pairs": ([p, p, p, p, i64, p, p, i64, i32, p, p], ctypes.c_int),
         "ft_last_rerank_stats": ([p, p], ctypes.c_int),
+        "ft_last_quadtree_stats": ([p, p], ctypes.c_int),
         "ft_quadtree_eps_pairs": ([p, p, p, p, i64, p, p, i64, ctypes.c_double, p, p], ctypes.c_int),
         "ft_quadtree_eps_knn": ([p, p, p, p, i64, p, i32, ctypes.c_double, i32, p, p, p], ctypes.c_int),
         "ft_exact_knn": ([p, p, p, p, i64, p, i32, i32, p, p, p], ctypes.c_int),
@@ -149,6 +150,13 @@ class Index:
         buf = ctypes.create_string_buffer(256)
         _check(load().ft_last_batched_stats(self._h, ctypes.byref(ms), buf, 256))
         return ms.value, buf.value.decode()
+
+    def last_select_exact_rows(self):
+        """Rows of the last quadtree_knn call whose sampled one-pass select
+        fell back to the exact select."""
+        n = ctypes.c_int64(0)
+        _check(load().ft_last_quadtree_stats(self._h, ctypes.byref(n)))
+        return n.value
 
     def last_rerank_ms(self):
         """Device time of the estimate kernels of the last act_knn or

@@ -138,11 +138,15 @@ struct ft_index {
                            // cell mass; by slice, then cell, then doc
   ft::DevBuf post_dir;     // u32 [post_nsl * post_cells] end offset of each cell's list in its slice
   ft::DevBuf post_cbase;   // u32 [32] first cell number of each depth
+  ft::DevBuf post_head;     // u32 [post_nsl][post_nhead][post_slice] dense cell masses of the head cells, by doc
+  ft::DevBuf post_hcell;    // u8 [post_cells] head index of each cell (0xFF: a listed cell)
   int64_t post_slice = 0, post_cells = 0, post_nsl = 0;
+  int32_t post_nhead = 0;
   // per-call workspaces
   ft::Dists qry;
   ft::DevBuf ws_keys, ws_cost, ws_tiles, ws_lists, ws_counts, ws_misc, ws_sel, ws_rerank;
   ft::DevBuf ws_gx64, ws_adj, ws_glist;  // backward: fixed-point dX, per-pair weight adjoints, pair lists
+  ft::DevBuf sel_exact;  // u32: rows of the last all-docs Quadtree select that took the exact path
   ft::DevBuf fwd_id, fwd_eta, fwd_key, fwd_bind, fwd_cnt, fwd_base;  // saved flows (FT_FWD)
   int64_t fwd_pairs = 0, fwd_cap = 0;
   ft::DevBuf fwd_sig;          // copies of the FT_FWD query CSR and pairs

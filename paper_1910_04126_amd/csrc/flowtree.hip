@@ -76,10 +76,9 @@ __global__ __launch_bounds__(64 * W) void k_flow_plain(PairArgs a, int64_t q) {
 // Persistent: workgroups grab chunks of the class's pair list until it is
 // used up.
 template <int C, int W, int G>
-__global__ __launch_bounds__(64 * W, (flow_min_waves<C, W>())) void k_flow_persistent(PairArgs a, const int64_t* __restrict__ list,
-                                                            const int64_t* __restrict__ offsets, int64_t n_q, int cls,
-                                                            uint32_t* __restrict__ counters, int chunk) {
-  __shared__ FlowLds<C, W> L;
+__device__ __forceinline__ void persistent_body(FlowLds<C, W>& L, const PairArgs& a, const int64_t* __restrict__ list,
+                                                const int64_t* __restrict__ offsets, int64_t n_q, int cls,
+                                                uint32_t* __restrict__ counters, int chunk) {
   const int64_t begin = offsets[(int64_t)cls * n_q], end = offsets[(int64_t)(cls + 1) * n_q];
   while (true) {
     if (threadIdx.x == 0) L.work = (int64_t)atomicAdd(&counters[cls], 1u);
@@ -90,6 +89,25 @@ __global__ __launch_bounds__(64 * W, (flow_min_waves<C, W>())) void k_flow_persi
     const int64_t i1 = min(end, i0 + chunk);
     for (int64_t i = i0; i < i1; ++i) flow_one<C, W, G>(L, a, list[i]);
   }
+}
+
+template <int C, int W, int G>
+__global__ __launch_bounds__(64 * W, (flow_min_waves<C, W>())) void k_flow_persistent(PairArgs a, const int64_t* __restrict__ list,
+                                                            const int64_t* __restrict__ offsets, int64_t n_q, int cls,
+                                                            uint32_t* __restrict__ counters, int chunk) {
+  __shared__ FlowLds<C, W> L;
+  persistent_body<C, W, G>(L, a, list, offsets, n_q, cls, counters, chunk);
+}
+
+// The smallest class (one wavefront, 2 items per lane) fits seven
+// wavefronts per SIMD by its vector registers; its scalar registers are held
+// to 72 so that they do not cap it lower.
+template <int G>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_num_sgpr(72))) void k_flow_persistent_small(
+    PairArgs a, const int64_t* __restrict__ list, const int64_t* __restrict__ offsets, int64_t n_q, int cls,
+    uint32_t* __restrict__ counters, int chunk) {
+  __shared__ FlowLds<2, 1> L;
+  persistent_body<2, 1, G>(L, a, list, offsets, n_q, cls, counters, chunk);
 }
 
 // All pairs of one size class out of a flat list of n_pairs (query p /
@@ -214,7 +232,8 @@ static const void* persistent_kernel(int cls, int G) {
   with_class(cls, [&](auto cc, auto ww) {
     with_lanes(G, [&](auto gg) {
       constexpr int C = decltype(cc)::value, W = decltype(ww)::value, GG = decltype(gg)::value;
-      fn = reinterpret_cast<const void*>(&k_flow_persistent<C, W, GG>);
+      if constexpr (C == 2 && W == 1) fn = reinterpret_cast<const void*>(&k_flow_persistent_small<GG>);
+      else fn = reinterpret_cast<const void*>(&k_flow_persistent<C, W, GG>);
     });
   });
   return fn;
@@ -225,7 +244,10 @@ static void launch_persistent(int cls, int G, unsigned blocks, const PairArgs& a
   with_class(cls, [&](auto cc, auto ww) {
     with_lanes(G, [&](auto gg) {
       constexpr int C = decltype(cc)::value, W = decltype(ww)::value, GG = decltype(gg)::value;
-      k_flow_persistent<C, W, GG><<<blocks, 64 * W, 0, s>>>(a, list, offsets, n_q, cls, counters, chunk);
+      if constexpr (C == 2 && W == 1)
+        k_flow_persistent_small<GG><<<blocks, 64, 0, s>>>(a, list, offsets, n_q, cls, counters, chunk);
+      else
+        k_flow_persistent<C, W, GG><<<blocks, 64 * W, 0, s>>>(a, list, offsets, n_q, cls, counters, chunk);
     });
   });
 }

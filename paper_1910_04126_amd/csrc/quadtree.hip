@@ -144,6 +144,17 @@ constexpr int QP_PIECE = 256;    // list entries per piece
 constexpr int QP_U = 2;          // pieces in flight per wavefront
 // a list in a slice has at most one entry per doc
 constexpr int QP_MAX_PIECES = QP_ENTRIES * (QP_ACC_BYTES / 4) / QP_PIECE;
+// Head cells: a few cells are touched by a large share of all docs and carry
+// most of the list entries (on word-embedding-shaped data the 64 longest
+// lists hold about 70 % of the (query, doc, shared cell) work).  For the
+// cells touched by at least half of the docs (up to QP_HEAD_MAX) a slice
+// keeps a dense row of cell masses, one u32 per doc, and each thread adds
+// its own 16 docs' terms in registers: no atomics for those cells.  Half is
+// where a dense row stops costing more than the list it replaces (measured:
+// a quarter and three quarters were both slower).  Only with narrow counters
+// over full 8192-doc slices.
+constexpr int QP_HEAD_MAX = 64;
+constexpr int QP_HEAD_SLICE = 8192;  // QP_THREADS threads x 16 docs
 
 inline bool post_narrow(int Q, int height) { return Q + height <= 32; }
 // With Q + height <= 31 every key U < 2^(Q + height + 1) once expressed in
@@ -236,19 +247,39 @@ __global__ __launch_bounds__(64) void k_post_fill(const int64_t* __restrict__ eo
   }
 }
 
+// Wavefront per doc: its masses in the head cells, into the dense rows of
+// its slice (rows start zeroed).
+__global__ __launch_bounds__(64) void k_head_fill(const int64_t* __restrict__ eoff, const uint32_t* __restrict__ ekey,
+                                                  const uint32_t* __restrict__ emass, int64_t n_docs,
+                                                  const uint32_t* __restrict__ cbase, const uint8_t* __restrict__ hcell,
+                                                  int nhead, uint32_t* __restrict__ rows) {
+  for (int64_t d = blockIdx.x; d < n_docs; d += gridDim.x) {
+    const int64_t sl = d / QP_HEAD_SLICE, local = d - sl * QP_HEAD_SLICE;
+    for (int64_t e = eoff[d] + lane_id(); e < eoff[d + 1]; e += 64) {
+      const uint8_t h = hcell[cell_number(cbase, ekey[e])];
+      if (h != 0xFFu) rows[((size_t)sl * nhead + h) * QP_HEAD_SLICE + local] = emass[e];
+    }
+  }
+}
+
 // Workgroup per (query, slice).  Workgroups are dealt to the 8 XCDs in turn,
 // so block b runs on XCD b % 8; slices are given out so that each XCD walks
 // one slice at a time through all the queries of the launch, keeping that
 // slice's lists in its L2.  H: the tree height (narrow counters).
-template <bool NARROW, bool COMPACT>
-__global__ __launch_bounds__(QP_THREADS) void k_qt_post(
+// Held to 72 scalar registers: at 82 the kernel allocated 96 and ran
+// 15 % slower (fewer workgroups per CU), although its vector registers and
+// LDS allow four.
+template <bool NARROW, bool COMPACT, bool HEAD>
+__global__ __launch_bounds__(QP_THREADS) __attribute__((amdgpu_num_sgpr(72))) void k_qt_post(
     const uint16_t* __restrict__ post_doc, const uint32_t* __restrict__ post_mass, const uint32_t* __restrict__ dir,
-    const uint32_t* __restrict__ cbase,
+    const uint32_t* __restrict__ cbase, const uint32_t* __restrict__ head_rows, const uint8_t* __restrict__ hcell,
+    int nhead,
     int64_t n_cells, int64_t S, int64_t n_sl, const int64_t* __restrict__ d_eoff, const uint64_t* __restrict__ d_S,
     int64_t n_docs, const int64_t* __restrict__ q_eoff, const uint32_t* __restrict__ q_ekey,
     const uint32_t* __restrict__ q_emass, const uint64_t* __restrict__ q_S, int64_t r0, int64_t n_rows, int B, int H,
     void* __restrict__ keys_out, unsigned long long* __restrict__ minmax) {
   static_assert(NARROW || !COMPACT, "compact keys need narrow counters");
+  static_assert(NARROW || !HEAD, "dense head rows need narrow counters");
   using Acc = typename std::conditional<NARROW, uint32_t, unsigned long long>::type;
   using Key = typename std::conditional<COMPACT, uint32_t, uint64_t>::type;
   constexpr int SMAX = QP_ACC_BYTES / sizeof(Acc);
@@ -266,20 +297,77 @@ __global__ __launch_bounds__(QP_THREADS) void k_qt_post(
   const int tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
   const int64_t q = r0 + row, d0 = sl * S;
   const int nd = (int)(n_docs - d0 < S ? n_docs - d0 : S);
-  for (int i = tid; i < nd; i += QP_THREADS) acc[i] = 0;
   const uint32_t* D = dir + sl * n_cells;
   const uint16_t* Pd = post_doc + d_eoff[d0];
   const uint32_t* Pm = post_mass + d_eoff[d0];
   const int64_t e0 = q_eoff[q];
   const int ne = (int)(q_eoff[q + 1] - e0);
   const int top = NARROW ? H : B;
+  if constexpr (HEAD) {
+    // the query's head cells (any order: the sums are exact integers)
+    __shared__ uint32_t hq_mass[QP_HEAD_MAX];
+    __shared__ uint8_t hq_id[QP_HEAD_MAX], hq_sh[QP_HEAD_MAX];
+    __shared__ int n_hq;
+    if (tid == 0) n_hq = 0;
+    __syncthreads();
+    for (int e = tid; e < ne; e += QP_THREADS) {
+      const uint32_t key = q_ekey[e0 + e];
+      const uint8_t h = hcell[cell_number(cbase, key)];
+      if (h != 0xFFu) {
+        const int i = atomicAdd(&n_hq, 1);
+        hq_id[i] = h;
+        hq_mass[i] = q_emass[e0 + e];
+        hq_sh[i] = (uint8_t)(top - (int)(key >> KEY_DEPTH_SHIFT));
+      }
+    }
+    __syncthreads();
+    // thread t owns docs j * 2048 + 4t + k (j, k < 4): its row reads are
+    // 16 bytes at consecutive addresses across the wavefront
+    const int nh = n_hq;
+    const uint32_t* rows = head_rows + (size_t)sl * nhead * QP_HEAD_SLICE + 4 * tid;
+    Acc a16[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) a16[k] = 0;
+    for (int i = 0; i < nh; i += 2) {
+      uint4 v[2][4];
+      uint32_t am[2], sh[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const bool live = i + u < nh;
+        const uint32_t* r = rows + (size_t)(live ? hq_id[i + u] : 0) * QP_HEAD_SLICE;
+        am[u] = live ? hq_mass[i + u] : 0u;
+        sh[u] = live ? hq_sh[i + u] : 0u;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[u][j] = live ? *reinterpret_cast<const uint4*>(r + j * 2048) : make_uint4(0, 0, 0, 0);
+      }
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          a16[4 * j + 0] += (Acc)min(am[u], v[u][j].x) << sh[u];
+          a16[4 * j + 1] += (Acc)min(am[u], v[u][j].y) << sh[u];
+          a16[4 * j + 2] += (Acc)min(am[u], v[u][j].z) << sh[u];
+          a16[4 * j + 3] += (Acc)min(am[u], v[u][j].w) << sh[u];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int doc = j * 2048 + 4 * tid + k;
+        if (doc < nd) acc[doc] = a16[4 * j + k];
+      }
+  } else {
+    for (int i = tid; i < nd; i += QP_THREADS) acc[i] = 0;
+  }
   for (int c0 = 0; c0 < ne; c0 += QP_ENTRIES) {
     if (tid == 0) ctr = 0ull;
     __syncthreads();
     if (tid < QP_ENTRIES && c0 + tid < ne) {
       const uint32_t key = q_ekey[e0 + c0 + tid];
       const uint32_t c = cell_number(cbase, key);
-      const uint32_t o1 = D[c], o0 = c ? D[c - 1] : 0u;
+      const bool listed = !HEAD || hcell[c] == 0xFFu;
+      const uint32_t o1 = listed ? D[c] : 0u, o0 = listed && c ? D[c - 1] : 0u;
       if (o1 > o0) {
         const uint32_t len = o1 - o0, np = (len + QP_PIECE - 1) / QP_PIECE;
         const unsigned long long old = atomicAdd(&ctr, (1ull << 32) | np);
@@ -363,6 +451,8 @@ __global__ __launch_bounds__(QP_THREADS) void k_qt_post(
     atomicMax(&minmax[2 * row + 1], mx);
   }
 }
+
+__global__ void k_zero_u32(uint32_t* __restrict__ p) { *p = 0u; }
 
 __global__ void k_minmax_init(unsigned long long* __restrict__ minmax, int64_t rows) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -508,6 +598,38 @@ static void prepare_postings(ft_index* ix, hipStream_t s) {
   ix->post_slice = S;
   ix->post_cells = n_cells;
   ix->post_nsl = n_sl;
+  // head cells: touched by at least half of the docs, the longest
+  // first (ties by cell number), at most QP_HEAD_MAX; dense rows only with
+  // narrow counters over full 8192-doc slices
+  ix->post_nhead = 0;
+  if (!narrow || S != QP_HEAD_SLICE) return;
+  std::vector<uint32_t> hdir(n_sl * n_cells);
+  FT_HIP(hipMemcpy(hdir.data(), dir, hdir.size() * 4, hipMemcpyDeviceToHost));
+  std::vector<int64_t> total(n_cells, 0);
+  for (int64_t sl = 0; sl < n_sl; ++sl)
+    for (int64_t c = 0; c < n_cells; ++c)
+      total[c] += hdir[sl * n_cells + c] - (c ? hdir[sl * n_cells + c - 1] : 0u);
+  std::vector<int64_t> cand;
+  for (int64_t c = 0; c < n_cells; ++c)
+    if (2 * total[c] >= n) cand.push_back(c);
+  std::sort(cand.begin(), cand.end(), [&](int64_t a, int64_t b) {
+    return total[a] != total[b] ? total[a] > total[b] : a < b;
+  });
+  if (cand.size() > (size_t)QP_HEAD_MAX) cand.resize(QP_HEAD_MAX);
+  if (cand.empty()) return;
+  const int nh = (int)cand.size();
+  std::vector<uint8_t> hc(n_cells, 0xFFu);
+  for (int h = 0; h < nh; ++h) hc[cand[h]] = (uint8_t)h;
+  uint8_t* hcell = (uint8_t*)ix->post_hcell.ensure(n_cells);
+  FT_HIP(hipMemcpy(hcell, hc.data(), n_cells, hipMemcpyHostToDevice));
+  const size_t rows_bytes = (size_t)n_sl * nh * QP_HEAD_SLICE * 4;
+  uint32_t* rows = (uint32_t*)ix->post_head.ensure(rows_bytes);
+  FT_HIP(hipMemsetAsync(rows, 0, rows_bytes, s));
+  k_head_fill<<<g, 64, 0, s>>>(ix->docs.ecnt.as<int64_t>(), ix->docs.ekey.as<uint32_t>(),
+                              ix->docs.emass.as<uint32_t>(), n, cbase, hcell, nh, rows);
+  FT_HIP(hipGetLastError());
+  FT_HIP(hipStreamSynchronize(s));
+  ix->post_nhead = nh;
 }
 
 }  // namespace ft
@@ -565,6 +687,10 @@ extern "C" ft_status ft_quadtree_knn(ft_index* ix, const int64_t* q_off, const u
       k_minmax_init<<<(unsigned)ceil_div(mm_rows, 256), 256, 0, s>>>(minmax_base, mm_rows);
       FT_HIP(hipGetLastError());
     }
+    // rows whose sampled select falls back to the exact path, counted
+    uint32_t* sel_exact = (uint32_t*)ix->sel_exact.ensure(4);
+    k_zero_u32<<<1, 1, 0, s>>>(sel_exact);
+    FT_HIP(hipGetLastError());
     const int64_t n_chunks = ceil_div(n_q, rows_per_chunk);
     int64_t chunk = 0;
     for (int64_t r0 = 0; r0 < n_q; r0 += rows_per_chunk, ++chunk) {
@@ -580,18 +706,23 @@ extern "C" ft_status ft_quadtree_knn(ft_index* ix, const int64_t* q_off, const u
         // the buffers of chunk - 2 must have been read by its select (and
         // the key ranges emptied again)
         if (pipe && chunk >= 2) FT_HIP(hipStreamWaitEvent(s, ix->ev_sel[b], 0));
-        auto go = [&](auto narrow, auto packed) {
-          k_qt_post<decltype(narrow)::value, decltype(packed)::value><<<(unsigned)(groups * 8 * rows), QP_THREADS, 0, s>>>(
+        auto go = [&](auto narrow, auto packed, auto head) {
+          k_qt_post<decltype(narrow)::value, decltype(packed)::value, decltype(head)::value>
+              <<<(unsigned)(groups * 8 * rows), QP_THREADS, 0, s>>>(
               ix->post.as<uint16_t>(),
               (const uint32_t*)((const char*)ix->post.p + ((std::max<int64_t>(1, ix->docs.emb_nnz) * 2 + 15) & ~int64_t(15))),
-              ix->post_dir.as<uint32_t>(), ix->post_cbase.as<uint32_t>(), ix->post_cells,
+              ix->post_dir.as<uint32_t>(), ix->post_cbase.as<uint32_t>(), ix->post_head.as<uint32_t>(),
+              ix->post_hcell.as<uint8_t>(), ix->post_nhead, ix->post_cells,
               ix->post_slice, ix->post_nsl, ix->docs.ecnt.as<int64_t>(), ix->docs.S.as<uint64_t>(), n_cols,
               ix->qry.ecnt.as<int64_t>(), ix->qry.ekey.as<uint32_t>(), ix->qry.emass.as<uint32_t>(),
               ix->qry.S.as<uint64_t>(), r0, rows, ix->B, ix->height, keys, minmax);
         };
-        if (compact) go(std::true_type{}, std::true_type{});
-        else if (post_narrow(ix->Q, ix->height)) go(std::true_type{}, std::false_type{});
-        else go(std::false_type{}, std::false_type{});
+        const bool head = ix->post_nhead > 0;
+        if (compact && head) go(std::true_type{}, std::true_type{}, std::true_type{});
+        else if (compact) go(std::true_type{}, std::true_type{}, std::false_type{});
+        else if (post_narrow(ix->Q, ix->height) && head) go(std::true_type{}, std::false_type{}, std::true_type{});
+        else if (post_narrow(ix->Q, ix->height)) go(std::true_type{}, std::false_type{}, std::false_type{});
+        else go(std::false_type{}, std::false_type{}, std::false_type{});
         FT_HIP(hipGetLastError());
       } else {
         // candidate lists: one query per workgroup, its table in LDS
@@ -626,10 +757,11 @@ extern "C" ft_status ft_quadtree_knn(ft_index* ix, const int64_t* q_off, const u
       }
       if (compact)
         topk_rows(reinterpret_cast<const uint32_t*>(keys), r1 - r0, n_cols, nullptr, k, out_key + r0 * k,
-                  ix->B - ix->height, out_doc + r0 * k, ckey_tmp, s_sel, reinterpret_cast<const uint64_t*>(minmax));
+                  ix->B - ix->height, out_doc + r0 * k, ckey_tmp, s_sel, reinterpret_cast<const uint64_t*>(minmax),
+                  sel_exact);
       else
         topk_rows(keys, r1 - r0, n_cols, cand ? cand + r0 * n_cols : nullptr, k, out_key + r0 * k, out_doc + r0 * k,
-                  s_sel, reinterpret_cast<const uint64_t*>(minmax));
+                  s_sel, reinterpret_cast<const uint64_t*>(minmax), sel_exact);
       if (minmax && pipe && chunk + 2 < n_chunks) {
         k_minmax_init<<<(unsigned)ceil_div(rows_per_chunk, 256), 256, 0, s_sel>>>(minmax, rows_per_chunk);
         FT_HIP(hipGetLastError());
@@ -728,5 +860,14 @@ extern "C" ft_status ft_quadtree_eps_knn(ft_index* ix, const int64_t* q_off, con
       topk_rows(cost, r1 - r0, n_cand, cand + r0 * n_cand, k, out_cost + r0 * k, out_doc + r0 * k, s);
     }
     FT_HIP(hipStreamSynchronize(s));
+  });
+}
+
+extern "C" ft_status ft_last_quadtree_stats(const ft_index* ix, int64_t* select_exact_rows) {
+  return guarded([&] {
+    FT_REQUIRE(ix && select_exact_rows, FT_EINVAL, "NULL argument");
+    uint32_t v = 0;
+    if (ix->sel_exact.p) FT_HIP(hipMemcpy(&v, ix->sel_exact.p, 4, hipMemcpyDeviceToHost));
+    *select_exact_rows = v;
   });
 }

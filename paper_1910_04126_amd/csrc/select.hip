@@ -90,10 +90,13 @@ constexpr int COLLECT_CAP = 4096;  // keys gathered by the one-pass path (a powe
 // bits inside it, ...) holding the target-th smallest key, until that bucket
 // holds at most stop keys or the last bit is reached.  On return, keys with
 // shr64(x, hs) < sel number `below`, and those equal to sel number `nties`.
+// Columns: [0, n_cols) when bstride == 16, else the n_cols / 16 blocks of 16
+// consecutive columns starting every bstride columns (a sample spread over
+// the whole row; bstride a multiple of 16).
 template <class K>
-__device__ void digit_levels(const K* __restrict__ rk, int64_t n_cols, uint32_t target, uint32_t stop, int& hs,
-                             uint64_t& sel, uint32_t& below, uint32_t& nties, uint32_t* hist, uint32_t* s_b,
-                             uint32_t* s_below) {
+__device__ void digit_levels(const K* __restrict__ rk, int64_t n_cols, int64_t bstride, uint32_t target,
+                             uint32_t stop, int& hs, uint64_t& sel, uint32_t& below, uint32_t& nties,
+                             uint32_t* hist, uint32_t* s_b, uint32_t* s_below) {
   constexpr int W = 11;
   int lo = hs - W;
   below = 0;
@@ -110,7 +113,7 @@ __device__ void digit_levels(const K* __restrict__ rk, int64_t n_cols, uint32_t 
       if ((n_cols & 3) == 0 && (reinterpret_cast<uintptr_t>(rk) & 15) == 0) {
         const uint4* r4 = reinterpret_cast<const uint4*>(rk);
         for (int64_t c = threadIdx.x; c < (n_cols >> 2); c += blockDim.x) {
-          const uint4 v = r4[c];
+          const uint4 v = r4[(c >> 2) * (bstride >> 2) + (c & 3)];
           count(sort_bits_of<K>(v.x));
           count(sort_bits_of<K>(v.y));
           count(sort_bits_of<K>(v.z));
@@ -120,7 +123,7 @@ __device__ void digit_levels(const K* __restrict__ rk, int64_t n_cols, uint32_t 
       }
     }
     if (!done)
-      for (int64_t c = threadIdx.x; c < n_cols; c += blockDim.x) count(sort_bits(rk[c]));
+      for (int64_t c = threadIdx.x; c < n_cols; c += blockDim.x) count(sort_bits(rk[(c >> 4) * bstride + (c & 15)]));
     __syncthreads();
     if (threadIdx.x < 64) {
       const int per = (1 << W) / 64;
@@ -154,10 +157,11 @@ __device__ void digit_levels(const K* __restrict__ rk, int64_t n_cols, uint32_t 
 
 // Rows longer than SMALL_MAX.  All keys share the bits above the highest bit
 // where the row's min and max differ (given, or found in a first pass).
-//  * One-pass path: digit histograms over a contiguous prefix of the row (a
-//    sixteenth, at least 16384 columns; the whole row when short) find a
-//    threshold below which a little more than k * prefix / n of the prefix
-//    keys lie; one pass over the row gathers every key at or below it into
+//  * One-pass path: digit histograms over a sample of the row (blocks of 16
+//    consecutive columns spread evenly over the whole row, a sixteenth of it
+//    and at least 16384 columns; the whole row when short) find a threshold
+//    below which a little more than k * sample / n of the sample keys lie;
+//    one pass over the row gathers every key at or below it into
 //    LDS.  When that gathers between k and COLLECT_CAP keys, the k smallest
 //    are among them (every key left out is larger than every key taken), and
 //    a sort of the gathered keys finishes the row.
@@ -170,7 +174,8 @@ __device__ void digit_levels(const K* __restrict__ rk, int64_t n_cols, uint32_t 
 template <class K>
 __global__ __launch_bounds__(1024) void k_topk_window(const K* __restrict__ keys, int64_t n, int k,
                                                       const uint64_t* __restrict__ minmax,
-                                                      K* __restrict__ out_key, int64_t* __restrict__ out_doc) {
+                                                      K* __restrict__ out_key, int64_t* __restrict__ out_doc,
+                                                      uint32_t* __restrict__ exact_rows) {
   constexpr int W = 11;
   __shared__ uint32_t hist[1 << W];
   __shared__ uint64_t bufk[COLLECT_CAP];
@@ -223,12 +228,16 @@ __global__ __launch_bounds__(1024) void k_topk_window(const K* __restrict__ keys
 
   // ---- one-pass path
   {
-    const int64_t ns = n <= 65536 ? n : (n / 16 > 16384 ? n / 16 : 16384);
+    // sample: nb blocks of 16 columns, one every bstride columns
+    const int64_t want = n <= 65536 ? n : (n / 16 > 16384 ? n / 16 : 16384);
+    const int64_t nb = want == n ? 0 : want / 16;
+    const int64_t bstride = nb ? (n / nb) & ~int64_t(15) : 16;
+    const int64_t ns = nb ? nb * 16 : n;
     const uint32_t target =
         ns == n ? (uint32_t)k : (uint32_t)min((int64_t)ns, (int64_t)k * ns / n * 115 / 100 + 16);
     hs = hs0;
     sel = shr64(mn, hs0);
-    digit_levels(rk, ns, target, 16u, hs, sel, below, nties, hist, &s_b, &s_below);
+    digit_levels(rk, ns, bstride, target, 16u, hs, sel, below, nties, hist, &s_b, &s_below);
     if (threadIdx.x == 0) s_nl = 0;
     __syncthreads();
     auto collect = [&](uint64_t x, int64_t c) {
@@ -278,9 +287,10 @@ __global__ __launch_bounds__(1024) void k_topk_window(const K* __restrict__ keys
   }
 
   // ---- exact path
+  if (exact_rows && threadIdx.x == 0) atomicAdd(exact_rows, 1u);
   hs = hs0;
   sel = shr64(mn, hs0);
-  digit_levels(rk, n, (uint32_t)k, (uint32_t)TIE_CAP, hs, sel, below, nties, hist, &s_b, &s_below);
+  digit_levels(rk, n, 16, (uint32_t)k, (uint32_t)TIE_CAP, hs, sel, below, nties, hist, &s_b, &s_below);
   if (threadIdx.x == 0) s_nl = s_nt = 0;
   __syncthreads();
   const bool many = nties > TIE_CAP;  // then every tie key is the same value
@@ -354,7 +364,7 @@ __global__ __launch_bounds__(1024) void k_topk_window(const K* __restrict__ keys
 
 template <class K>
 static void topk_rows_impl(const K* keys, int64_t rows, int64_t n, const int64_t* docs, int k, K* out_key,
-                           int64_t* out_doc, const uint64_t* minmax, hipStream_t s) {
+                           int64_t* out_doc, const uint64_t* minmax, hipStream_t s, uint32_t* exact_rows) {
   FT_REQUIRE(k >= 1 && k <= n, FT_EINVAL, "k must lie in [1, number of candidates]");
   if (rows <= 0) return;
   if (n <= SMALL_MAX) {
@@ -362,14 +372,14 @@ static void topk_rows_impl(const K* keys, int64_t rows, int64_t n, const int64_t
   } else {
     FT_REQUIRE(docs == nullptr, FT_ERANGE, "candidate lists longer than 4096 are not supported");
     FT_REQUIRE(k <= 1024, FT_ERANGE, "k > 1024 needs at most 4096 candidates");
-    k_topk_window<K><<<(unsigned)rows, 1024, 0, s>>>(keys, n, k, minmax, out_key, out_doc);
+    k_topk_window<K><<<(unsigned)rows, 1024, 0, s>>>(keys, n, k, minmax, out_key, out_doc, exact_rows);
   }
   FT_HIP(hipGetLastError());
 }
 
 void topk_rows(const uint64_t* keys, int64_t rows, int64_t n, const int64_t* docs, int k, uint64_t* out_key,
-               int64_t* out_doc, hipStream_t s, const uint64_t* minmax) {
-  topk_rows_impl<uint64_t>(keys, rows, n, docs, k, out_key, out_doc, minmax, s);
+               int64_t* out_doc, hipStream_t s, const uint64_t* minmax, uint32_t* exact_rows) {
+  topk_rows_impl<uint64_t>(keys, rows, n, docs, k, out_key, out_doc, minmax, s, exact_rows);
 }
 
 __global__ void k_widen_keys(const uint32_t* __restrict__ in, int64_t n, int shift, uint64_t* __restrict__ out) {
@@ -378,8 +388,8 @@ __global__ void k_widen_keys(const uint32_t* __restrict__ in, int64_t n, int shi
 }
 
 void topk_rows(const uint32_t* keys, int64_t rows, int64_t n, const int64_t* docs, int k, uint64_t* out_key, int shift,
-               int64_t* out_doc, uint32_t* tmp_key, hipStream_t s, const uint64_t* minmax) {
-  topk_rows_impl<uint32_t>(keys, rows, n, docs, k, tmp_key, out_doc, minmax, s);
+               int64_t* out_doc, uint32_t* tmp_key, hipStream_t s, const uint64_t* minmax, uint32_t* exact_rows) {
+  topk_rows_impl<uint32_t>(keys, rows, n, docs, k, tmp_key, out_doc, minmax, s, exact_rows);
   if (rows > 0) {
     k_widen_keys<<<(unsigned)ceil_div(rows * k, 256), 256, 0, s>>>(tmp_key, rows * k, shift, out_key);
     FT_HIP(hipGetLastError());
@@ -388,7 +398,7 @@ void topk_rows(const uint32_t* keys, int64_t rows, int64_t n, const int64_t* doc
 
 void topk_rows(const float* keys, int64_t rows, int64_t n, const int64_t* docs, int k, float* out_key,
                int64_t* out_doc, hipStream_t s) {
-  topk_rows_impl<float>(keys, rows, n, docs, k, out_key, out_doc, nullptr, s);
+  topk_rows_impl<float>(keys, rows, n, docs, k, out_key, out_doc, nullptr, s, nullptr);
 }
 
 }  // namespace ft
