@@ -44,27 +44,27 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 
-# HBM bytes of one launch of the persistent Flowtree graph on the batched
-# workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a 1 GiB copy
-# (profiles/flowtree_batched_uneven_hbm_traffic.md), valid while the kernel
+# HBM bytes of one launch of the persistent Flowtree graph per workload, from
+# rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a 1 GiB copy
+# (profiles/flowtree_quadtree_batched_hbm_traffic.md), valid while the kernel
 # sources hash to TRAFFIC_SOURCES_SHA1.
-TRAFFIC_BYTES = 2.783e+11
+TRAFFIC_BYTES = {"batched": 2.7498e+11, "batched_v1m": 4.1620e+11}
 TRAFFIC_SOURCES = ("paper_1910_04126_amd/csrc/flow.h", "paper_1910_04126_amd/csrc/flowtree.hip",
                    "paper_1910_04126_amd/csrc/wave.h", "paper_1910_04126_amd/csrc/common.h")
-TRAFFIC_SOURCES_SHA1 = "702b6f3941dd9d237625072ec6c946b0a9a13b4f"
+TRAFFIC_SOURCES_SHA1 = "48234b915ae1701a2fc8657d04b0344662588139"
 
 
 def measured_traffic(workload):
     """The counted bytes when they were taken on this workload and these
     kernel sources, else None."""
     import hashlib
-    if workload != "batched":
+    if workload not in TRAFFIC_BYTES:
         return None
     h = hashlib.sha1()
     for f in TRAFFIC_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    return TRAFFIC_BYTES if h.hexdigest() == TRAFFIC_SOURCES_SHA1 else None
+    return TRAFFIC_BYTES[workload] if h.hexdigest() == TRAFFIC_SOURCES_SHA1 else None
 
 
 def log(*a):

@@ -600,7 +600,7 @@ extern "C" ft_status ft_build_tree(const float* X, int64_t V, int32_t d, const i
     try {
       ix->V = V;
       ix->d = d;
-      ix->dp = (d + 3) / 4 * 4;
+      ix->dp = padded_row(d);
       ix->B = B;
       ix->Q = Q;
       FT_HIP(hipGetDevice(&ix->device));

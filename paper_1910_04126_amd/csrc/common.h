@@ -123,7 +123,7 @@ struct ft_index {
   hipStream_t work = nullptr;  // internal stream for graph capture
   hipEvent_t ev_a = nullptr, ev_b = nullptr, ev_t0 = nullptr, ev_t1 = nullptr;
   hipEvent_t ev_rank[2] = {nullptr, nullptr}, ev_sel[2] = {nullptr, nullptr};  // Quadtree chunk pipeline
-  ft::DevBuf Xm;        // float [V * dp], Morton order, rows padded to dp
+  ft::DevBuf Xm;        // float [V * dp], Morton order, rows zero-padded to dp = padded_row(d)
   ft::DevBuf Xn;        // double [V] squared norms of the Xm rows
   ft::DevBuf perm;      // u32 [V] rank -> original id
   ft::DevBuf inv;       // u32 [V] original id -> rank
@@ -181,6 +181,17 @@ __device__ __forceinline__ int lca_depth(const uint8_t* __restrict__ st, int64_t
 }
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Row length in floats of the index's Morton-ordered coordinate copy: d
+// rounded up so that the G lanes that share a row in the Flowtree pricing
+// (the power of two up to 16 that covers the row in float4s) read the same
+// number of float4s each; the padding is zero.
+inline int padded_row(int d) {
+  const int nv = (d + 3) / 4;
+  int g = 1;
+  while (g < 16 && g < nv) g <<= 1;
+  return (int)ceil_div(nv, g) * g * 4;
+}
 
 // Host helpers implemented in build.hip.
 void prepare_dists(ft_index* ix, Dists& D, const int64_t* off, const uint32_t* id,

@@ -81,7 +81,8 @@ __device__ __forceinline__ void flow_stage(FlowLds<C, W>& L, const uint32_t* __r
 }
 
 // The greedy flow of a staged pair; returns the number of matches in
-// L.em_pos / L.em_eta (uniform across the workgroup).
+// L.em_pos / L.em_eta (uniform across the workgroup).  Without SAVE the list
+// leaves out the matches between equal ranks, whose distance is 0.
 template <int C, int W, bool SAVE>
 __device__ int flow_match(FlowLds<C, W>& L, const int nq, const int nd, const uint8_t* __restrict__ st,
                           const int64_t V, const int B, FlowSave sv, uint32_t* __restrict__ status) {
@@ -284,6 +285,9 @@ __device__ int flow_match(FlowLds<C, W>& L, const int nq, const int nd, const ui
               const uint32_t lo_p = p == a0 ? 0u : L.pp[p - 1];
               own = lo_p != lo;
             }
+            // pricing-only runs drop a match between equal ranks (distance
+            // 0); only a segment of depth B can hold one
+            if (!SAVE && k == B) own = own && L.rank[t] != L.rank[p];
             if (own) {
               const uint32_t ho = opp[p];
               uint32_t end = hi < ho ? hi : ho;
@@ -376,6 +380,95 @@ __device__ __forceinline__ double row_sum_f64(double v) {
   return v;
 }
 
+// Pairs of matches that share the item of the smaller side (by_doc: the doc
+// item): a counting sort in LDS (res and slot are free once the matching is
+// done) groups the matches by that item, each item's run padded to even
+// length, and unit u is the two entries ord[2u], ord[2u + 1] of L.slot (the
+// second 0xFFFF when the run was odd).  The padded order needs up to
+// (n - 1) + n / 2 entries (at most n - 1 matches, at most n / 2 odd runs):
+// slot and the byte array after it (both dead by now) hold 1.5 N.  Returns
+// the number of units, uniform across the workgroup.
+template <int C, int W>
+__device__ int pair_units(FlowLds<C, W>& L, const int E, const int n, const bool by_doc,
+                          uint32_t* __restrict__ status) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  using Lds = FlowLds<C, W>;
+  static_assert(offsetof(Lds, lcn) == offsetof(Lds, slot) + 2 * Lds::N, "slot and lcn must be adjacent");
+  uint32_t* cnt = L.res;
+  uint16_t* ord = L.slot;
+  constexpr uint16_t NONE = 0xFFFFu;
+  for (int i = tid; i < n; i += 64 * W) cnt[i] = 0u;
+  __syncthreads();
+  for (int e = tid; e < E; e += 64 * W) {
+    const uint32_t pos = L.em_pos[e];
+    atomicAdd(&cnt[by_doc ? (pos & 0xFFFFu) : (pos >> 16)], 1u);
+  }
+  __syncthreads();
+  int units;
+  {
+    // exclusive scan of the even-rounded counts: thread t holds [t*C, t*C + C)
+    const int t0 = tid * C;
+    uint32_t v[C], tot = 0;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      v[c] = t0 + c < n ? (cnt[t0 + c] + 1u) & ~1u : 0u;
+      tot += v[c];
+    }
+    const uint32_t incl = wave_incl_sum(tot);
+    uint32_t base = incl - tot;
+    uint32_t all = __shfl(incl, 63, 64);
+    if (W > 1) {
+      if (lane == 63) L.x_c[w] = incl;
+      __syncthreads();
+      all = 0;
+      for (int j = 0; j < W; ++j) {
+        if (j < w) base += L.x_c[j];
+        all += L.x_c[j];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      if (t0 + c < n) cnt[t0 + c] = base;
+      base += v[c];
+    }
+    units = (int)(all >> 1);
+  }
+  if (2 * units > 3 * FlowLds<C, W>::N / 2) {
+    // cannot happen (the bound above); never overrun, report it instead
+    if (tid == 0) atomicOr(status, ERR_FLOW);
+    units = 0;
+  }
+  for (int i = tid; i < 2 * units; i += 64 * W) ord[i] = NONE;
+  __syncthreads();
+  for (int e = tid; e < E; e += 64 * W) {
+    const uint32_t pos = L.em_pos[e];
+    ord[atomicAdd(&cnt[by_doc ? (pos & 0xFFFFu) : (pos >> 16)], 1u)] = (uint16_t)e;
+  }
+  __syncthreads();
+  return units;
+}
+
+// The sum of the E per-match products in an order that depends on E only:
+// lane j of wavefront 0 adds the products j, j + 64, ... in turn, then the 64
+// lane sums are combined by a fixed tree (rows of 16 by DPP, then the four
+// rows).  Valid in wavefront 0.
+__device__ __forceinline__ double sum_products(const double* prod, const int E) {
+  double cost = 0.0;
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    for (int e0 = lane; e0 < E; e0 += 4 * 64) {
+      double v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = e0 + 64 * u < E ? prod[e0 + 64 * u] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) cost += v[u];
+    }
+    cost = row_sum_f64(cost);
+    cost = (__shfl(cost, 0, 64) + __shfl(cost, 16, 64)) + (__shfl(cost, 32, 64) + __shfl(cost, 48, 64));
+  }
+  return cost;
+}
+
 // Euclidean price of the matches: sum eta * ||x_doc - x_query||_2 (float32
 // distances, float64 accumulation).  G lanes share one match, and a lane
 // reads up to PV float4 (or floats when VEC == 1) of each row per pass, all
@@ -440,66 +533,12 @@ __device__ double flow_price(FlowLds<C, W>& L, const int E, const int nq, const 
     }
   } else {
     // Matches are priced two at a time that share the item of the smaller
-    // side: a counting sort in LDS (res and slot are free once the matching is
-    // done) groups them by that item, each item's run padded to even length,
-    // and a lane group then reads the shared row once for both (three rows for
-    // two matches).  Products stay indexed by match.  The padded order needs up
-    // to (n - 1) + n / 2 entries (at most n - 1 matches, at most n / 2 odd
-    // runs): slot and the byte array after it (both dead by now) hold 1.5 N.
-    using Lds = FlowLds<C, W>;
-    static_assert(offsetof(Lds, lcn) == offsetof(Lds, slot) + 2 * Lds::N, "slot and lcn must be adjacent");
-    uint32_t* cnt = L.res;
-    uint16_t* ord = L.slot;
-    constexpr uint16_t NONE = 0xFFFFu;
+    // side (pair_units), and a lane group reads the shared row once for both
+    // (three rows for two matches).  Products stay indexed by match.
     const bool by_doc = nd <= nq;
-    for (int i = tid; i < n; i += 64 * W) cnt[i] = 0u;
-    __syncthreads();
-    for (int e = tid; e < E; e += 64 * W) {
-      const uint32_t pos = L.em_pos[e];
-      atomicAdd(&cnt[by_doc ? (pos & 0xFFFFu) : (pos >> 16)], 1u);
-    }
-    __syncthreads();
-    int units;
-    {
-      // exclusive scan of the even-rounded counts: thread t holds [t*C, t*C + C)
-      const int t0 = tid * C;
-      uint32_t v[C], tot = 0;
-#pragma unroll
-      for (int c = 0; c < C; ++c) {
-        v[c] = t0 + c < n ? (cnt[t0 + c] + 1u) & ~1u : 0u;
-        tot += v[c];
-      }
-      const uint32_t incl = wave_incl_sum(tot);
-      uint32_t base = incl - tot;
-      uint32_t all = __shfl(incl, 63, 64);
-      if (W > 1) {
-        if (lane == 63) L.x_c[w] = incl;
-        __syncthreads();
-        all = 0;
-        for (int j = 0; j < W; ++j) {
-          if (j < w) base += L.x_c[j];
-          all += L.x_c[j];
-        }
-      }
-#pragma unroll
-      for (int c = 0; c < C; ++c) {
-        if (t0 + c < n) cnt[t0 + c] = base;
-        base += v[c];
-      }
-      units = (int)(all >> 1);
-    }
-    if (2 * units > 3 * FlowLds<C, W>::N / 2) {
-      // cannot happen (see above); never overrun, report it instead
-      if (tid == 0) atomicOr(status, ERR_FLOW);
-      units = 0;
-    }
-    for (int i = tid; i < 2 * units; i += 64 * W) ord[i] = NONE;
-    __syncthreads();
-    for (int e = tid; e < E; e += 64 * W) {
-      const uint32_t pos = L.em_pos[e];
-      ord[atomicAdd(&cnt[by_doc ? (pos & 0xFFFFu) : (pos >> 16)], 1u)] = (uint16_t)e;
-    }
-    __syncthreads();
+    const int units = pair_units(L, E, n, by_doc, status);
+    const uint16_t* ord = L.slot;
+    constexpr uint16_t NONE = 0xFFFFu;
     for (int u0 = 0; u0 < units; u0 += PER) {
       const int u = u0 + g;
       int e1 = E, e2 = E;
@@ -568,22 +607,115 @@ __device__ double flow_price(FlowLds<C, W>& L, const int E, const int nq, const 
     }
   }
   __syncthreads();
-  // a fixed order that depends on E only: lane j of wavefront 0 adds the
-  // products j, j + 64, ... in turn, then the 64 lane sums are combined by a
-  // fixed tree (rows of 16 by DPP, then the four rows)
-  double cost = 0.0;
-  if (tid < 64) {
-    for (int e0 = lane; e0 < E; e0 += 4 * 64) {
-      double v[4];
+  return sum_products(prod, E);
+}
+
+// squared distance of two float4 slices added to acc, one fma per component
+__device__ __forceinline__ float dist2_acc(float acc, const float4 a, const float4 b) {
+  const float dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z, dw = a.w - b.w;
+  acc = fmaf(dx, dx, acc);
+  acc = fmaf(dy, dy, acc);
+  acc = fmaf(dz, dz, acc);
+  return fmaf(dw, dw, acc);
+}
+
+// flow_price over the index's own coordinate copy: row r of X (Morton rank r)
+// holds `stride` floats, zero past d, with stride a multiple of 4 G, so each
+// lane of a group reads exactly stride / (4 G) float4 of a row and no load
+// needs a bound check; and the match list (flow_match without SAVE) holds no
+// zero-distance match, so no match is skipped.  A lane group that has no
+// match in a pass branches around its loads.  Products and their sum as in
+// flow_price.
+template <int C, int W, int G>
+__device__ double flow_price_tiled(FlowLds<C, W>& L, const int E, const int nq, const int nd,
+                                   const float* __restrict__ X, const int stride, uint32_t* __restrict__ status) {
+  constexpr int PER = 64 * W / G;
+  constexpr int PV = C * W >= 8 ? 5 : 2;
+  const int tid = threadIdx.x;
+  const int g = tid / G, sub = tid % G;
+  const int per = stride / (4 * G);  // float4 per lane per row
+  const int n = nq + nd;
+  double* prod = reinterpret_cast<double*>(L.pp);
+  if constexpr (C * W < 4) {
+    // short pairs: one match per lane group, in match order
+    for (int e0 = 0; e0 < E; e0 += PER) {
+      const int e = e0 + g;
+      float acc = 0.0f;
+      if (e < E) {
+        const uint32_t pos = L.em_pos[e];
+        const float4* pa = reinterpret_cast<const float4*>(X + (int64_t)L.rank[pos & 0xFFFFu] * stride) + sub;
+        const float4* pb = reinterpret_cast<const float4*>(X + (int64_t)L.rank[pos >> 16] * stride) + sub;
+        for (int b = 0; b < per; b += PV) {
+          float4 xa[PV], xb[PV];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) v[u] = e0 + 64 * u < E ? prod[e0 + 64 * u] : 0.0;
+          for (int t = 0; t < PV; ++t)
+            if (b + t < per) {
+              xa[t] = pa[(b + t) * G];
+              xb[t] = pb[(b + t) * G];
+            }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) cost += v[u];
+          for (int t = 0; t < PV; ++t)
+            if (b + t < per) acc = dist2_acc(acc, xa[t], xb[t]);
+        }
+      }
+      acc = group_sum<G>(acc);
+      if (sub == 0 && e < E) prod[e] = (double)L.em_eta[e] * (double)sqrtf(acc);
     }
-    cost = row_sum_f64(cost);
-    cost = (__shfl(cost, 0, 64) + __shfl(cost, 16, 64)) + (__shfl(cost, 32, 64) + __shfl(cost, 48, 64));
+  } else {
+    // two matches that share the item of the smaller side per lane group
+    // (pair_units); a unit that holds one match (the end of an odd run) reads
+    // the shared row in place of a second row, so every lane loads the same
+    // three rows (a masked third load measured slower) and the second sum, 0,
+    // is not stored
+    const bool by_doc = nd <= nq;
+    const int units = pair_units(L, E, n, by_doc, status);
+    const uint16_t* ord = L.slot;
+    for (int u0 = 0; u0 < units; u0 += PER) {
+      const int u = u0 + g;
+      int e1 = E, e2 = E;
+      float acc1 = 0.0f, acc2 = 0.0f;
+      if (u < units) {
+        e1 = ord[2 * u];
+        const uint16_t o2 = ord[2 * u + 1];
+        e2 = o2 == 0xFFFFu ? E : (int)o2;
+        const uint32_t pos1 = L.em_pos[e1];
+        const uint32_t rs = L.rank[by_doc ? (pos1 & 0xFFFFu) : (pos1 >> 16)];
+        const uint32_t r1 = L.rank[by_doc ? (pos1 >> 16) : (pos1 & 0xFFFFu)];
+        uint32_t r2 = rs;
+        if (e2 < E) {
+          const uint32_t pos2 = L.em_pos[e2];
+          r2 = L.rank[by_doc ? (pos2 >> 16) : (pos2 & 0xFFFFu)];
+        }
+        const float4* ps = reinterpret_cast<const float4*>(X + (int64_t)rs * stride) + sub;
+        const float4* p1 = reinterpret_cast<const float4*>(X + (int64_t)r1 * stride) + sub;
+        const float4* p2 = reinterpret_cast<const float4*>(X + (int64_t)r2 * stride) + sub;
+        for (int b = 0; b < per; b += PV) {
+          float4 xs[PV], x1[PV], x2[PV];
+#pragma unroll
+          for (int t = 0; t < PV; ++t)
+            if (b + t < per) {
+              xs[t] = ps[(b + t) * G];
+              x1[t] = p1[(b + t) * G];
+              x2[t] = p2[(b + t) * G];
+            }
+#pragma unroll
+          for (int t = 0; t < PV; ++t)
+            if (b + t < per) {
+              acc1 = dist2_acc(acc1, xs[t], x1[t]);
+              acc2 = dist2_acc(acc2, xs[t], x2[t]);
+            }
+        }
+      }
+      acc1 = group_sum<G>(acc1);
+      acc2 = group_sum<G>(acc2);
+      if (sub == 0) {
+        if (e1 < E) prod[e1] = (double)L.em_eta[e1] * (double)sqrtf(acc1);
+        if (e2 < E) prod[e2] = (double)L.em_eta[e2] * (double)sqrtf(acc2);
+      }
+    }
   }
-  return cost;
+  __syncthreads();
+  return sum_products(prod, E);
 }
 
 // Lanes per match from the row length in float4 units.

@@ -52,7 +52,7 @@ __device__ __forceinline__ void flow_one(FlowLds<C, W>& L, const PairArgs& a, co
   }
   flow_stage(L, a.q_rank + qa, a.q_mass + qa, nq, a.d_rank + da, a.d_mass + da, nd);
   const int E = flow_match<C, W, false>(L, nq, nd, a.st, a.V, a.B, FlowSave{}, a.status);
-  const double cost = flow_price<C, W, G, 4>(L, E, nq, nd, a.X, nullptr, a.stride, a.stride, a.status);
+  const double cost = flow_price_tiled<C, W, G>(L, E, nq, nd, a.X, a.stride, a.status);
   if (threadIdx.x == 0) a.cost[p] = (float)ldexp(cost, -a.Q);
   __syncthreads();
 }
