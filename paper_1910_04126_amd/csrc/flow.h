@@ -89,6 +89,11 @@ __device__ int flow_match(FlowLds<C, W>& L, const int nq, const int nd, const ui
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int n = nq + nd;
   const int t0 = tid * C;
+  // A thread's own items t0 + c keep their state in registers across the
+  // depths: unmatched mass, side, and the LCA depth with the next item.
+  uint32_t res[C];
+  bool isq[C];
+  int lcn[C];
   // ---- merge both supports by rank (doc first on equal ranks)
   {
     const uint32_t* qr = L.pp;
@@ -101,15 +106,19 @@ __device__ int flow_match(FlowLds<C, W>& L, const int nq, const int nd, const ui
       else hi = mid;
     }
     int j = lo, i = k0 - lo;
+#pragma unroll
     for (int c = 0; c < C; ++c) {
       const int t = t0 + c;
+      res[c] = 0u;
+      isq[c] = false;
       if (t < n) {
         const bool take_d = j < nd && (i >= nq || dr[j] <= qr[i]);
         const int s = take_d ? nq + j : i;
         if (take_d) ++j;
         else ++i;
         L.rank[t] = L.pp[s];
-        L.res[t] = L.pn[s];
+        res[c] = L.pn[s];
+        isq[c] = !take_d;
         L.slot[t] = (uint16_t)s;
       }
     }
@@ -141,23 +150,25 @@ __device__ int flow_match(FlowLds<C, W>& L, const int nq, const int nd, const ui
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       const int t = t0 + c;
-      if (t < n) {
-        int l = -1;
-        if (t + 1 < n) {
-          l = same[c] ? B : (va[c] < vb[c] ? va[c] : vb[c]);
-          mask |= 1u << l;
-        }
-        L.lcn[t] = (int8_t)l;
+      int l = -1;
+      if (t + 1 < n) {
+        l = same[c] ? B : (va[c] < vb[c] ? va[c] : vb[c]);
+        mask |= 1u << l;
       }
+      lcn[c] = l;
+      if (t < n) L.lcn[t] = (int8_t)l;
     }
   }
   mask = wave_or(mask);
   if (W > 1) {
     if (lane == 0) L.x_m[w] = mask;
-    __syncthreads();
-    for (int j = 0; j < W; ++j) mask |= L.x_m[j];
   }
   __syncthreads();
+  if (W > 1)
+    for (int j = 0; j < W; ++j) mask |= L.x_m[j];
+  // LCA depth of the item before this thread's first (-1 for item 0: every
+  // depth starts a segment there)
+  const int lcn_prev = (t0 > 0 && t0 <= n) ? (int)L.lcn[t0 - 1] : -1;
   int E = 0;
   while (mask) {
     const int k = 31 - __clz(mask);
@@ -165,17 +176,17 @@ __device__ int flow_match(FlowLds<C, W>& L, const int nq, const int nd, const ui
     // local segmented sums of this lane's items
     uint32_t run_p = 0, run_n = 0;
     int last_start = -1, first_end = 0x7FFFFFFF;
+#pragma unroll
     for (int c = 0; c < C; ++c) {
       const int t = t0 + c;
       if (t < n) {
-        if (t == 0 || L.lcn[t - 1] < k) {
+        if ((c ? lcn[c - 1] : lcn_prev) < k) {
           run_p = run_n = 0;
           last_start = t;
         }
-        const uint32_t r = L.res[t];
-        if (L.slot[t] < nq) run_n += r;
-        else run_p += r;
-        if (L.lcn[t] < k && first_end == 0x7FFFFFFF) first_end = t;
+        if (isq[c]) run_n += res[c];
+        else run_p += res[c];
+        if (lcn[c] < k && first_end == 0x7FFFFFFF) first_end = t;
       }
     }
     uint32_t tp = run_p, tn = run_n;
@@ -208,101 +219,125 @@ __device__ int flow_match(FlowLds<C, W>& L, const int nq, const int nd, const ui
         tn += kn;
       }
     }
-    uint32_t cp = __shfl_up(tp, 1, 64), cn = __shfl_up(tn, 1, 64);
-    int prev_start = max(ks, __shfl_up(ls_incl, 1, 64));
-    int next_end = min(ke, __shfl_down(fe_suf, 1, 64));
+    // exclusive carries: lane 0 takes the other wavefronts', lane 63's next
+    // end comes from them
+    uint32_t cp = wave_shr1(tp, kp), cn = wave_shr1(tn, kn);
+    int prev_start = max(ks, wave_shr1(ls_incl, ks));
+    int next_end = min(ke, wave_shl1(fe_suf, ke));
     if (lane == 0) {
       cp = kp;
       cn = kn;
       prev_start = ks;
     }
     if (lane == 63) next_end = ke;
-    // inclusive prefixes with the carry from earlier lanes; segment bounds
-    uint32_t se[C];
+    // inclusive prefixes with the carry from earlier lanes, into LDS for the
+    // searches of other items and into registers for this lane's own
+    uint32_t hi[C];
+    int a0[C], e0[C];
     run_p = cp;
     run_n = cn;
     int s0 = prev_start;
+#pragma unroll
     for (int c = 0; c < C; ++c) {
       const int t = t0 + c;
-      se[c] = 0;
+      hi[c] = 0u;
+      a0[c] = 0;
       if (t < n) {
-        if (t == 0 || L.lcn[t - 1] < k) {
+        if ((c ? lcn[c - 1] : lcn_prev) < k) {
           run_p = run_n = 0;
           s0 = t;
         }
-        const uint32_t r = L.res[t];
-        if (L.slot[t] < nq) run_n += r;
-        else run_p += r;
+        if (isq[c]) run_n += res[c];
+        else run_p += res[c];
         L.pp[t] = run_p;
         L.pn[t] = run_n;
-        se[c] = (uint32_t)s0;
+        hi[c] = isq[c] ? run_n : run_p;
+        a0[c] = s0;
       }
     }
     {
       int e = next_end;
+#pragma unroll
       for (int c = C - 1; c >= 0; --c) {
-        const int t = t0 + c;
-        if (t < n) {
-          if (L.lcn[t] < k) e = t;
-          se[c] |= (uint32_t)e << 16;
-        }
+        if (lcn[c] < k) e = t0 + c;
+        e0[c] = t0 + c < n ? e : 0;
       }
     }
     __syncthreads();
-    // each item finds the match that starts at its own interval start
-    uint32_t m_pos[C], m_eta[C], m_lo[C];
+    // each item with mass left finds the match that starts at its own
+    // interval start: the first item of the other side in its segment whose
+    // inclusive prefix exceeds that start.  The searches of a lane's items run
+    // side by side, a fixed number of halvings each (branch-free lower bound
+    // over [a0, e0], whose last prefix, the side's total, exceeds the start).
+    uint32_t lo[C], M[C];
+    int base[C], len[C];
+    bool want[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const uint32_t Tp = L.pp[e0[c]], Tn = L.pn[e0[c]];
+      M[c] = Tp < Tn ? Tp : Tn;
+      lo[c] = hi[c] - res[c];
+      want[c] = t0 + c < n && res[c] > 0u && lo[c] < M[c];
+      base[c] = a0[c];
+      len[c] = want[c] ? e0[c] - a0[c] + 1 : 1;
+    }
+    int span = 1;
+#pragma unroll
+    for (int c = 0; c < C; ++c) span = max(span, len[c]);
+    span = lane_value(wave_incl_max(span), 63);
+    while (span > 1) {
+      uint32_t v[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const int half = len[c] >> 1;
+        const uint32_t* opp = isq[c] ? L.pp : L.pn;
+        v[c] = opp[base[c] + (half > 0 ? half - 1 : 0)];
+      }
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const int half = len[c] >> 1;
+        if (half > 0 && v[c] <= lo[c]) base[c] += half;
+        len[c] -= half;
+      }
+      span -= span >> 1;
+    }
+    // the match found: a query item yields to a doc item that starts at the
+    // same point (that doc item owns the match)
+    uint32_t m_pos[C], m_eta[C];
     uint8_t m_bind[C];
     int cnt = 0;
-    for (int c = 0; c < C; ++c) {
-      const int t = t0 + c;
-      m_eta[c] = 0;
-      m_pos[c] = 0;
-      m_lo[c] = 0;
-      m_bind[c] = 0;
-      if (t < n) {
-        const uint32_t r = L.res[t];
-        if (r > 0) {
-          const bool isq = L.slot[t] < nq;
-          const int a0 = (int)(se[c] & 0xFFFFu), e0 = (int)(se[c] >> 16);
-          const uint32_t Tp = L.pp[e0], Tn = L.pn[e0];
-          const uint32_t M = Tp < Tn ? Tp : Tn;
-          const uint32_t hi = isq ? L.pn[t] : L.pp[t];
-          const uint32_t lo = hi - r;
-          // set for every item, owner or not: with the store only on the
-          // owner's path, builds saved wrong starts for query-owned matches
-          m_lo[c] = lo;
-          if (lo < M) {
-            const uint32_t* opp = isq ? L.pp : L.pn;
-            int a = a0, b = e0;
-            while (a < b) {
-              const int mid = (a + b) >> 1;
-              if (opp[mid] > lo) b = mid;
-              else a = mid + 1;
-            }
-            const int p = a;
-            bool own = true;
-            if (isq) {
-              const uint32_t lo_p = p == a0 ? 0u : L.pp[p - 1];
-              own = lo_p != lo;
-            }
-            // pricing-only runs drop a match between equal ranks (distance
-            // 0); only a segment of depth B can hold one
-            if (!SAVE && k == B) own = own && L.rank[t] != L.rank[p];
-            if (own) {
-              const uint32_t ho = opp[p];
-              uint32_t end = hi < ho ? hi : ho;
-              end = end < M ? end : M;
-              m_eta[c] = end - lo;
-              m_pos[c] = isq ? ((uint32_t)p | ((uint32_t)t << 16)) : ((uint32_t)t | ((uint32_t)p << 16));
-              if (SAVE) {
-                const uint32_t hd = isq ? ho : hi, hq = isq ? hi : ho;
-                m_bind[c] = (end == hd && end == hq) ? 2 : (end == hd ? 0 : 1);
-              }
-              ++cnt;
-            }
+    {
+      uint32_t ho[C], lp[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const int p = base[c];
+        const uint32_t* opp = isq[c] ? L.pp : L.pn;
+        ho[c] = opp[p];
+        lp[c] = L.pp[p > a0[c] ? p - 1 : p];
+      }
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const int t = t0 + c, p = base[c];
+        m_eta[c] = 0;
+        m_pos[c] = 0;
+        m_bind[c] = 0;
+        bool own = want[c];
+        if (isq[c]) own = own && (p == a0[c] ? 0u : lp[c]) != lo[c];
+        // pricing-only runs drop a match between equal ranks (distance 0);
+        // only a segment of depth B can hold one
+        if (!SAVE && k == B && own) own = L.rank[t] != L.rank[p];
+        if (own) {
+          uint32_t end = hi[c] < ho[c] ? hi[c] : ho[c];
+          end = end < M[c] ? end : M[c];
+          m_eta[c] = end - lo[c];
+          m_pos[c] = isq[c] ? ((uint32_t)p | ((uint32_t)t << 16)) : ((uint32_t)t | ((uint32_t)p << 16));
+          if (SAVE) {
+            const uint32_t hd = isq[c] ? ho[c] : hi[c], hq = isq[c] ? hi[c] : ho[c];
+            m_bind[c] = (end == hd && end == hq) ? 2 : (end == hd ? 0 : 1);
           }
-          L.res[t] = hi > M ? hi - (lo > M ? lo : M) : 0u;
+          ++cnt;
         }
+        if (t0 + c < n && res[c] > 0u) res[c] = hi[c] > M[c] ? hi[c] - (lo[c] > M[c] ? lo[c] : M[c]) : 0u;
       }
     }
     const int incl = wave_incl_sum(cnt);
@@ -316,9 +351,10 @@ __device__ int flow_match(FlowLds<C, W>& L, const int nq, const int nd, const ui
         total += (int)L.x_c[j];
       }
     } else {
-      total = __shfl(incl, 63, 64);
+      total = lane_value(incl, 63);
     }
     int off = E + before + incl - cnt;
+#pragma unroll
     for (int c = 0; c < C; ++c) {
       if (m_eta[c]) {
         L.em_pos[off] = m_pos[c];
@@ -328,7 +364,7 @@ __device__ int flow_match(FlowLds<C, W>& L, const int nq, const int nd, const ui
           const uint32_t pd = m_pos[c] & 0xFFFFu, pq = m_pos[c] >> 16;
           sv.id[g] = ((uint32_t)(L.slot[pd] - nq) << 16) | (uint32_t)L.slot[pq];
           sv.eta[g] = m_eta[c];
-          sv.key[g] = ((uint64_t)(31 - k) << 48) | ((uint64_t)(se[c] & 0xFFFFu) << 32) | m_lo[c];
+          sv.key[g] = ((uint64_t)(31 - k) << 48) | ((uint64_t)a0[c] << 32) | lo[c];
           sv.bind[g] = m_bind[c];
         }
         ++off;
@@ -339,8 +375,9 @@ __device__ int flow_match(FlowLds<C, W>& L, const int nq, const int nd, const ui
   }
   // every unit of mass must have been matched by the root
   bool left = false;
+#pragma unroll
   for (int c = 0; c < C; ++c)
-    if (t0 + c < n && L.res[t0 + c] != 0) left = true;
+    if (t0 + c < n && res[c] != 0u) left = true;
   if (__ballot(left) && lane == 0) atomicOr(status, ERR_FLOW);
   return E;
 }
