@@ -57,14 +57,51 @@ TRAFFIC_SOURCES_SHA1 = "48234b915ae1701a2fc8657d04b0344662588139"
 def measured_traffic(workload):
     """The counted bytes when they were taken on this workload and these
     kernel sources, else None."""
-    import hashlib
     if workload not in TRAFFIC_BYTES:
         return None
+    return TRAFFIC_BYTES[workload] if _sources_sha1(TRAFFIC_SOURCES) == TRAFFIC_SOURCES_SHA1 else None
+
+
+# Counters of the Quadtree prune stage per workload (two query chunks per
+# step: k_qt_post ranks, k_topk_window selects), from rocprofv3 --pmc runs
+# (profiles/quadtree_prune_batched_counters.md), valid while the prune
+# sources hash to PRUNE_SOURCES_SHA1: HBM bytes per step (FETCH_SIZE and
+# WRITE_SIZE scaled by the 1 GiB copy), and the ranking kernel's LDS busy
+# share of cycles, bank-conflict share of LDS cycles, VALU issue share and
+# L2 hit rate.
+PRUNE_COUNTERS = {}
+PRUNE_SOURCES = ("paper_1910_04126_amd/csrc/quadtree.hip", "paper_1910_04126_amd/csrc/select.hip",
+                 "paper_1910_04126_amd/csrc/wave.h", "paper_1910_04126_amd/csrc/common.h")
+PRUNE_SOURCES_SHA1 = ""
+
+
+def _sources_sha1(files):
+    import hashlib
     h = hashlib.sha1()
-    for f in TRAFFIC_SOURCES:
+    for f in files:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    return TRAFFIC_BYTES[workload] if h.hexdigest() == TRAFFIC_SOURCES_SHA1 else None
+    return h.hexdigest()
+
+
+def prune_roofline(workload, stage_ms, n_q, n_docs):
+    """The prune stage against the HBM peak: the bytes every pair must move
+    with materialised keys (a 4-byte key written, then read by the select),
+    and, when taken on these sources, the counted HBM bytes and the ranking
+    kernel's counters that name its bound (LDS atomics and L2 latency)."""
+    alg = 8.0 * n_q * n_docs
+    r = {"bound": "lds", "kernel": "k_qt_post + k_topk_window (both query chunks)",
+         "stage_ms": round(stage_ms, 3), "algorithmic_bytes": alg,
+         "achieved": round(alg / (stage_ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "frac": round(alg / (stage_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "traffic": None}
+    c = PRUNE_COUNTERS.get(workload)
+    if c and _sources_sha1(PRUNE_SOURCES) == PRUNE_SOURCES_SHA1:
+        r["traffic"] = c["bytes"]
+        r["counted_hbm_gbs"] = round(c["bytes"] / (stage_ms * 1e-3) / 1e9, 1)
+        r["counted_hbm_frac"] = round(r["counted_hbm_gbs"] / HBM_PEAK_GBS, 4)
+        for key in ("lds_busy", "lds_bank_conflict", "valu_issue", "l2_hit"):
+            r[key] = c[key]
+    return r
 
 
 def log(*a):
@@ -156,11 +193,20 @@ def main():
     stage_qt, stage_ft, kernel_ms, sel_exact = [], [], [], []
 
     def step():
-        ev[0].record()
+        """One pass of the whole path: with a prune, the one-call pipeline
+        (queries prepared once, flags read once); without, the batched
+        Flowtree over all docs."""
         if prune:
-            _, cand = ft.quadtree_knn(ix, qo, qi, qm, prune)
-        else:
-            cand = None
+            return ft.knn_pipeline(ix, qo, qi, qm, prune, k)
+        ev[1].record()
+        out = ft.flowtree_knn(ix, qo, qi, qm, k, mode=ft.FT_BATCHED)
+        ev[2].record()
+        return out
+
+    def two_calls():
+        """The same path as two calls (prune, then rerank the candidates)."""
+        ev[0].record()
+        _, cand = ft.quadtree_knn(ix, qo, qi, qm, prune)
         ev[1].record()
         costs, docs = ft.flowtree_knn(ix, qo, qi, qm, k, cand=cand, mode=ft.FT_BATCHED)
         ev[2].record()
@@ -168,16 +214,20 @@ def main():
 
     log("warmup x%d (the first call tunes the batched schedule)" % args.warmup)
     for _ in range(max(1, args.warmup)):
-        cand, costs, docs = step()
+        costs, docs = step()
     torch.cuda.synchronize()
     log("timing %d steps" % args.steps)
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for i in range(args.steps):
-        cand, costs, docs = step()
+        costs, docs = step()
         torch.cuda.synchronize()
-        stage_qt.append(ev[0].elapsed_time(ev[1]))
-        stage_ft.append(ev[1].elapsed_time(ev[2]))
+        if prune:
+            qt_ms, ft_ms = ix.last_pipeline_stats()
+        else:
+            qt_ms, ft_ms = 0.0, ev[1].elapsed_time(ev[2])
+        stage_qt.append(qt_ms)
+        stage_ft.append(ft_ms)
         kernel_ms.append(ix.last_batched_stats()[0])
         sel_exact.append(ix.last_select_exact_rows() if prune else 0)
         log("  step %d: quadtree %.1f ms, flowtree %.1f ms (persistent kernels %.1f ms)" % (
@@ -185,6 +235,23 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     ms_step = 1000.0 * elapsed / args.steps
+    cand = None
+    two_call = None
+    if prune:
+        # the same steps as two calls: the candidates for the byte count and
+        # the plain schedule, and the step time the one-call pipeline saves
+        cand, c2, d2 = two_calls()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for i in range(args.steps):
+            cand, c2, d2 = two_calls()
+            torch.cuda.synchronize()
+        two_ms = 1000.0 * (time.perf_counter() - t2) / args.steps
+        same = bool(torch.equal(d2, docs) and torch.equal(c2.view(torch.int32), costs.view(torch.int32)))
+        two_call = {"ms_per_step": round(two_ms, 3), "pipeline_ms_per_step": round(ms_step, 3),
+                    "identical_output": same}
+        log("two calls: %.1f ms per step vs one-call pipeline %.1f ms (identical output: %s)" % (
+            two_ms, ms_step, same))
     n_cols = prune if prune else ds.n_docs
     ft_pairs = n_q * n_cols
     value = ft_pairs / (elapsed / args.steps)
@@ -244,6 +311,7 @@ def main():
                    "prune_k": prune, "k": k, "flowtree_pairs_per_step": ft_pairs},
         "roofline": roofline_block(achieved, kms, alg_bytes, measured_traffic(args.workload), copy_gbs,
                                    "k_flow_persistent (all size classes, one graph)"),
+        "roofline_prune": prune_roofline(args.workload, float(np.mean(stage_qt)), n_q, ds.n_docs) if prune else None,
         "stages": {"quadtree_prune_ms": round(float(np.mean(stage_qt)), 3),
                    "prune_select_exact_rows": int(np.max(sel_exact)) if sel_exact else 0,
                    "quadtree_pairs_per_s": round(n_q * ds.n_docs / (float(np.mean(stage_qt)) * 1e-3), 1)
@@ -251,6 +319,7 @@ def main():
                    "flowtree_batched_ms": round(float(np.mean(stage_ft)), 3),
                    "flowtree_batched_pairs_per_s": round(ft_pairs / (float(np.mean(stage_ft)) * 1e-3), 1),
                    "schedule": schedule},
+        "two_calls": two_call,
         "plain": plain,
         "cpu_baseline": cpu,
         "index": info,

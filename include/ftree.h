@@ -142,6 +142,31 @@ ft_status ft_flowtree_knn(ft_index* index, const int64_t* q_off, const uint32_t*
                           int32_t n_cand, int32_t k, int32_t mode, float* out_cost,
                           int64_t* out_doc, void* stream);
 
+
+/* ------------------------------------------------------------------------
+ * ft_knn_pipeline -- the two-stage search of Section 4.3: the Quadtree
+ * estimate (Section 2) ranks every dataset distribution and keeps the
+ * prune_k best per query, then the Flowtree estimate (Section 3, greedy of
+ * Appendix A.1) reranks those and returns the k best.
+ *
+ * Queries as ft_quadtree_knn.  1 <= k <= prune_k <= min(number of docs,
+ * 4096); prune_k <= 1024 when there are more than 4096 docs.
+ * out_cost[n_q*k], out_doc[n_q*k] as ft_flowtree_knn (FT_BATCHED); they
+ * equal ft_flowtree_knn(cand = the doc lists of ft_quadtree_knn(k =
+ * prune_k)) bit for bit.  The queries are prepared once for both stages and
+ * the validation and kernel flags are read once, at the end; the candidate
+ * lists, which the call makes itself, are not checked again.  Device
+ * scratch of n_q * prune_k * 16 bytes is kept with the index.
+ * Errors: as ft_quadtree_knn and ft_flowtree_knn.
+ * ---------------------------------------------------------------------- */
+ft_status ft_knn_pipeline(ft_index* index, const int64_t* q_off, const uint32_t* q_id,
+                          const uint32_t* q_mass, int64_t n_q, int32_t prune_k, int32_t k,
+                          float* out_cost, int64_t* out_doc, void* stream);
+
+/* Host timing of the last ft_knn_pipeline call (milliseconds, HIP events on
+ * its stream): the Quadtree stage (ranking and select) and the Flowtree
+ * stage (batched rerank and select).  Either pointer may be NULL. */
+ft_status ft_last_pipeline_stats(const ft_index* index, double* prune_ms, double* rerank_ms);
 /* ------------------------------------------------------------------------
  * ft_flowtree_knn_noalloc -- ft_flowtree_knn over candidate lists for callers
  * that cannot allocate device memory (tight serving loops, harnesses that

@@ -54,6 +54,8 @@ def load():
         "ft_quadtree_knn": ([p, p, p, p, i64, p, i32, i32, p, p, p], ctypes.c_int),
         "ft_flowtree_knn": ([p, p, p, p, i64, p, i32, i32, i32, p, p, p], ctypes.c_int),
         "ft_flowtree_knn_noalloc": ([p, p, p, p, i64, p, i32, i32, p, p, p], ctypes.c_int),
+        "ft_knn_pipeline": ([p, p, p, p, i64, i32, i32, p, p, p], ctypes.c_int),
+        "ft_last_pipeline_stats": ([p, p, p], ctypes.c_int),
         "ft_flowtree_cost_grad": ([p, p, p, p, p, i64, p, p, i64, i32, p, p, p, p, p, p], ctypes.c_int),
         "ft_flowtree_flows": ([p, p, p, p, i64, p, p, i64, p, p, p, p, p, p, p], ctypes.c_int),
         "ft_quadtree_pairs": ([p, p, p, p, i64, p, p, i64, p, p], ctypes.c_int),
@@ -151,6 +153,12 @@ class Index:
         _check(load().ft_last_batched_stats(self._h, ctypes.byref(ms), buf, 256))
         return ms.value, buf.value.decode()
 
+    def last_pipeline_stats(self):
+        """(prune ms, rerank ms) of the last knn_pipeline call (HIP events)."""
+        a, b = ctypes.c_double(0.0), ctypes.c_double(0.0)
+        _check(load().ft_last_pipeline_stats(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
     def last_select_exact_rows(self):
         """Rows of the last quadtree_knn call whose sampled one-pass select
         fell back to the exact select."""
@@ -214,6 +222,19 @@ def flowtree_knn(index: Index, q_off, q_id, q_mass, k: int, cand=None, mode: int
     docs = torch.empty((n_q, k), dtype=torch.int64, device=dev)
     _check(load().ft_flowtree_knn(index.handle, _ptr(q_off), _ptr(q_id), _ptr(q_mass), n_q,
                                   _ptr(cand_t), n_cand, k, mode, _ptr(costs), _ptr(docs), _stream()))
+    return costs, docs
+
+
+def knn_pipeline(index: Index, q_off, q_id, q_mass, prune_k: int, k: int):
+    """ft_knn_pipeline -> (costs float32 [n_q, k], docs int64 [n_q, k]): the
+    Quadtree prune of every doc to prune_k, then the batched Flowtree rerank
+    to k, in one call."""
+    q_off, q_id, q_mass = _queries(q_off, q_id, q_mass)
+    n_q = q_off.numel() - 1
+    costs = torch.empty((n_q, k), dtype=torch.float32, device=q_off.device)
+    docs = torch.empty((n_q, k), dtype=torch.int64, device=q_off.device)
+    _check(load().ft_knn_pipeline(index.handle, _ptr(q_off), _ptr(q_id), _ptr(q_mass), n_q, prune_k, k,
+                                  _ptr(costs), _ptr(docs), _stream()))
     return costs, docs
 
 

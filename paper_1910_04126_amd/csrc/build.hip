@@ -562,7 +562,7 @@ extern "C" const char* ft_last_error(void) { return ft::g_last_error.c_str(); }
 extern "C" void ft_free(ft_index* ix) {
   if (!ix) return;
   ix->graphs.reset();
-  for (DevBuf* b : {&ix->post, &ix->post_dir, &ix->post_cbase, &ix->post_head, &ix->post_hcell, &ix->Xm, &ix->Xn, &ix->perm, &ix->inv, &ix->st, &ix->leafd, &ix->anc, &ix->status, &ix->ws_keys,
+  for (DevBuf* b : {&ix->post, &ix->post_dir, &ix->post_cbase, &ix->post_head, &ix->post_hcell, &ix->ws_pipe, &ix->Xm, &ix->Xn, &ix->perm, &ix->inv, &ix->st, &ix->leafd, &ix->anc, &ix->status, &ix->ws_keys,
                     &ix->ws_cost, &ix->ws_tiles, &ix->ws_lists, &ix->ws_counts, &ix->ws_misc, &ix->ws_sel, &ix->ws_rerank,
                     &ix->ws_gx64, &ix->ws_adj, &ix->ws_glist, &ix->sel_exact,
                     &ix->fwd_id, &ix->fwd_eta, &ix->fwd_key, &ix->fwd_bind, &ix->fwd_cnt, &ix->fwd_base, &ix->fwd_sig})
@@ -573,6 +573,8 @@ extern "C" void ft_free(ft_index* ix) {
   if (ix->ev_b) (void)hipEventDestroy(ix->ev_b);
   if (ix->ev_t0) (void)hipEventDestroy(ix->ev_t0);
   if (ix->ev_t1) (void)hipEventDestroy(ix->ev_t1);
+  for (hipEvent_t e : ix->ev_p)
+    if (e) (void)hipEventDestroy(e);
   for (int i = 0; i < 2; ++i) {
     if (ix->ev_rank[i]) (void)hipEventDestroy(ix->ev_rank[i]);
     if (ix->ev_sel[i]) (void)hipEventDestroy(ix->ev_sel[i]);
@@ -611,6 +613,7 @@ extern "C" ft_status ft_build_tree(const float* X, int64_t V, int32_t d, const i
       FT_HIP(hipEventCreateWithFlags(&ix->ev_b, hipEventDisableTiming));
       FT_HIP(hipEventCreate(&ix->ev_t0));
       FT_HIP(hipEventCreate(&ix->ev_t1));
+      for (hipEvent_t& e : ix->ev_p) FT_HIP(hipEventCreate(&e));
       for (int i = 0; i < 2; ++i) {
         FT_HIP(hipEventCreateWithFlags(&ix->ev_rank[i], hipEventDisableTiming));
         FT_HIP(hipEventCreateWithFlags(&ix->ev_sel[i], hipEventDisableTiming));

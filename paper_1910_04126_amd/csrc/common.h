@@ -123,6 +123,7 @@ struct ft_index {
   hipStream_t work = nullptr;  // internal stream for graph capture
   hipEvent_t ev_a = nullptr, ev_b = nullptr, ev_t0 = nullptr, ev_t1 = nullptr;
   hipEvent_t ev_rank[2] = {nullptr, nullptr}, ev_sel[2] = {nullptr, nullptr};  // Quadtree chunk pipeline
+  hipEvent_t ev_p[3] = {nullptr, nullptr, nullptr};  // ft_knn_pipeline: prune / rerank boundaries
   ft::DevBuf Xm;        // float [V * dp], Morton order, rows zero-padded to dp = padded_row(d)
   ft::DevBuf Xn;        // double [V] squared norms of the Xm rows
   ft::DevBuf perm;      // u32 [V] rank -> original id
@@ -146,6 +147,7 @@ struct ft_index {
   ft::Dists qry;
   ft::DevBuf ws_keys, ws_cost, ws_tiles, ws_lists, ws_counts, ws_misc, ws_sel, ws_rerank;
   ft::DevBuf ws_gx64, ws_adj, ws_glist;  // backward: fixed-point dX, per-pair weight adjoints, pair lists
+  ft::DevBuf ws_pipe;    // ft_knn_pipeline: prune keys, then candidate docs
   ft::DevBuf sel_exact;  // u32: rows of the last all-docs Quadtree select that took the exact path
   ft::DevBuf fwd_id, fwd_eta, fwd_key, fwd_bind, fwd_cnt, fwd_base;  // saved flows (FT_FWD)
   int64_t fwd_pairs = 0, fwd_cap = 0;
@@ -157,6 +159,7 @@ struct ft_index {
   ft::BatchedGraphs graphs;
   double last_batched_ms = 0.0;
   double last_rerank_ms = 0.0;  // device time of the last ACT / Sinkhorn knn kernels
+  double last_pipe_ms[2] = {0.0, 0.0};  // last ft_knn_pipeline: prune stage, rerank stage
   std::string last_schedule;
   std::mutex mu;
 };
@@ -207,6 +210,14 @@ void launch_prep_sort(const ft_index* ix, const int64_t* off, const uint32_t* id
 // Device address of the no-allocation entry point's scratch array on a
 // device (looked up once per device; that device must be current).
 void* noalloc_scratch(int device);
+
+// The bodies of ft_quadtree_knn and ft_flowtree_knn after their argument
+// checks, on queries already prepared in ix->qry (with the embedding for the
+// Quadtree) and candidate lists already checked; neither reads the status.
+void quadtree_knn_prepared(ft_index* ix, int64_t n_q, const int64_t* cand, int32_t n_cand, int32_t k,
+                           uint64_t* out_key, int64_t* out_doc, hipStream_t s);
+void flowtree_knn_prepared(ft_index* ix, int64_t n_q, const int64_t* cand, int32_t n_cand, int32_t k, int32_t mode,
+                           float* out_cost, int64_t* out_doc, hipStream_t s);
 int64_t scan_tmp_elems(int64_t n);
 void exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* tmp, hipStream_t s);
 uint32_t read_and_clear_status(ft_index* ix, hipStream_t s);

@@ -57,14 +57,15 @@ __device__ __forceinline__ void flow_one(FlowLds<C, W>& L, const PairArgs& a, co
   __syncthreads();
 }
 
-// Persistent workgroups of several wavefronts with 4 items per lane are
-// latency-bound on their row reads and LDS round trips: they are held to 96
-// VGPRs, five wavefronts per SIMD, the most their LDS allows.  The few
-// values that spill cost less than the extra wavefront gains (at 128 VGPRs
-// and four wavefronts per SIMD the batched kernels took 4 % longer and the
-// image-grid ones 13 %).
+// Persistent workgroups with 4 items per lane are latency-bound on their row
+// reads and LDS round trips: they are held to 96 VGPRs, five wavefronts per
+// SIMD (for W >= 2 the most their LDS allows).  The few values that spill
+// cost less than the extra wavefront gains (at 128 VGPRs and four wavefronts
+// per SIMD the batched kernels took 4 % longer and the image-grid ones 13 %;
+// the one-wavefront (4,1) class gained 2 % on the batched workload when held
+// to five).
 template <int C, int W>
-constexpr int flow_min_waves() { return (W >= 2 && C <= 4) ? 5 : 1; }
+constexpr int flow_min_waves() { return C == 4 ? 5 : 1; }
 
 // Plain: workgroup b handles column b of query q.
 template <int C, int W, int G>
@@ -356,7 +357,7 @@ static void flowtree_plain(ft_index* ix, const PairArgs& a, int64_t n_q, hipStre
   FT_HIP(hipMemcpyAsync(qoff.data(), a.q_off, (n_q + 1) * 8, hipMemcpyDeviceToHost, s));
   FT_HIP(hipMemcpyAsync(dmax.data(), dev_max, n_q * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   FT_HIP(hipStreamSynchronize(s));
-  const int G = lanes_for(ix->dp / 4);
+  const int G = knn_lanes(ix->dp);
   for (int64_t q = 0; q < n_q; ++q) {
     const int cls = class_for((int)(qoff[q + 1] - qoff[q]) + dmax[q]);
     FT_REQUIRE(cls >= 0, FT_ERANGE, "pair larger than 2048 items");
@@ -369,7 +370,7 @@ static void flowtree_batched(ft_index* ix, const PairArgs& a, int64_t n_q, hipSt
   const int64_t n_cols = a.n_cols;
   const int64_t npairs = n_q * n_cols;
   BatchedPlan P;
-  P.G = lanes_for(ix->dp / 4);
+  P.G = knn_lanes(ix->dp);
   P.n_q = n_q;
   P.n_cols = n_cols;
   const int64_t nc = (int64_t)N_CLASSES * n_q;
@@ -451,6 +452,40 @@ static void flowtree_batched(ft_index* ix, const PairArgs& a, int64_t n_q, hipSt
   FT_HIP(hipStreamWaitEvent(s, ix->ev_b, 0));
 }
 
+// ft_flowtree_knn after its argument checks, on the prepared queries
+// (ix->qry) and checked candidate lists; the caller reads the status.
+void ft::flowtree_knn_prepared(ft_index* ix, int64_t n_q, const int64_t* cand, int32_t n_cand, int32_t k, int32_t mode,
+                           float* out_cost, int64_t* out_doc, hipStream_t s) {
+  const int64_t n_cols = cand ? (int64_t)n_cand : ix->docs.n;
+  FT_REQUIRE(class_for(ix->qry.max_size + ix->docs.max_size) >= 0, FT_ERANGE, "pair larger than 2048 items");
+  // queries in chunks so the cost buffer stays near 1 GiB
+  const int64_t rows = std::max<int64_t>(1, std::min<int64_t>(n_q, (int64_t(1) << 28) / n_cols));
+  float* cost = (float*)ix->ws_cost.ensure(rows * n_cols * 4);
+  for (int64_t r0 = 0; r0 < n_q; r0 += rows) {
+    const int64_t r1 = std::min(n_q, r0 + rows);
+    PairArgs a;
+    a.q_off = ix->qry.off.as<int64_t>() + r0;
+    a.q_rank = ix->qry.rank.as<uint32_t>();
+    a.q_mass = ix->qry.mass.as<uint32_t>();
+    a.d_off = ix->docs.off.as<int64_t>();
+    a.d_rank = ix->docs.rank.as<uint32_t>();
+    a.d_mass = ix->docs.mass.as<uint32_t>();
+    a.cand = cand ? cand + r0 * n_cols : nullptr;
+    a.n_cols = n_cols;
+    a.st = ix->st.as<uint8_t>();
+    a.V = ix->V;
+    a.B = ix->B;
+    a.Q = ix->Q;
+    a.X = ix->Xm.as<float>();
+    a.stride = ix->dp;
+    a.status = ix->status.as<uint32_t>();
+    a.cost = cost;
+    if (mode == FT_PLAIN) flowtree_plain(ix, a, r1 - r0, s);
+    else flowtree_batched(ix, a, r1 - r0, s);
+    topk_rows(cost, r1 - r0, n_cols, a.cand, k, out_cost + r0 * k, out_doc + r0 * k, s);
+  }
+}
+
 extern "C" ft_status ft_flowtree_knn(ft_index* ix, const int64_t* q_off, const uint32_t* q_id, const uint32_t* q_mass,
                                      int64_t n_q, const int64_t* cand, int32_t n_cand, int32_t k, int32_t mode,
                                      float* out_cost, int64_t* out_doc, void* stream) {
@@ -465,39 +500,53 @@ extern "C" ft_status ft_flowtree_knn(ft_index* ix, const int64_t* q_off, const u
     FT_REQUIRE(cand || n_cols <= 4096 || k <= 1024, FT_ERANGE, "k > 1024 needs at most 4096 candidates");
     prepare_dists(ix, ix->qry, q_off, q_id, q_mass, n_q, false, s, "queries");
     if (cand) check_indices(ix, cand, n_q * n_cand, ix->docs.n, s, "cand");
-    FT_REQUIRE(class_for(ix->qry.max_size + ix->docs.max_size) >= 0, FT_ERANGE, "pair larger than 2048 items");
-    // queries in chunks so the cost buffer stays near 1 GiB
-    const int64_t rows = std::max<int64_t>(1, std::min<int64_t>(n_q, (int64_t(1) << 28) / n_cols));
-    float* cost = (float*)ix->ws_cost.ensure(rows * n_cols * 4);
-    for (int64_t r0 = 0; r0 < n_q; r0 += rows) {
-      const int64_t r1 = std::min(n_q, r0 + rows);
-      PairArgs a;
-      a.q_off = ix->qry.off.as<int64_t>() + r0;
-      a.q_rank = ix->qry.rank.as<uint32_t>();
-      a.q_mass = ix->qry.mass.as<uint32_t>();
-      a.d_off = ix->docs.off.as<int64_t>();
-      a.d_rank = ix->docs.rank.as<uint32_t>();
-      a.d_mass = ix->docs.mass.as<uint32_t>();
-      a.cand = cand ? cand + r0 * n_cols : nullptr;
-      a.n_cols = n_cols;
-      a.st = ix->st.as<uint8_t>();
-      a.V = ix->V;
-      a.B = ix->B;
-      a.Q = ix->Q;
-      a.X = ix->Xm.as<float>();
-      a.stride = ix->dp;
-      a.status = ix->status.as<uint32_t>();
-      a.cost = cost;
-      if (mode == FT_PLAIN) flowtree_plain(ix, a, r1 - r0, s);
-      else flowtree_batched(ix, a, r1 - r0, s);
-      topk_rows(cost, r1 - r0, n_cols, a.cand, k, out_cost + r0 * k, out_doc + r0 * k, s);
-    }
+    flowtree_knn_prepared(ix, n_q, cand, n_cand, k, mode, out_cost, out_doc, s);
     uint32_t flags = read_and_clear_status(ix, s);
     FT_REQUIRE(flags == 0, FT_EHIP, "flowtree kernel reported:" + describe_flags(flags));
     if (mode == FT_BATCHED) {
       float ms = 0.0f;
       if (hipEventElapsedTime(&ms, ix->ev_t0, ix->ev_t1) == hipSuccess) ix->last_batched_ms = ms;
     }
+  });
+}
+
+extern "C" ft_status ft_knn_pipeline(ft_index* ix, const int64_t* q_off, const uint32_t* q_id, const uint32_t* q_mass,
+                                     int64_t n_q, int32_t prune_k, int32_t k, float* out_cost, int64_t* out_doc,
+                                     void* stream) {
+  return guarded([&] {
+    FT_REQUIRE(ix && out_cost && out_doc, FT_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lock(ix->mu);
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n_docs = ix->docs.n;
+    FT_REQUIRE(prune_k >= 1 && prune_k <= n_docs, FT_EINVAL, "prune_k must lie in [1, number of docs]");
+    FT_REQUIRE(prune_k <= 4096, FT_ERANGE, "prune_k must be at most 4096");
+    FT_REQUIRE(n_docs <= 4096 || prune_k <= 1024, FT_ERANGE, "prune_k > 1024 needs at most 4096 docs");
+    FT_REQUIRE(k >= 1 && k <= prune_k, FT_EINVAL, "k must lie in [1, prune_k]");
+    // the queries are prepared once (validated, sorted, embedded) for both stages
+    prepare_dists(ix, ix->qry, q_off, q_id, q_mass, n_q, true, s, "queries");
+    uint64_t* keys = (uint64_t*)ix->ws_pipe.ensure(n_q * prune_k * 16);
+    int64_t* cand = reinterpret_cast<int64_t*>(keys + n_q * prune_k);
+    FT_HIP(hipEventRecord(ix->ev_p[0], s));
+    quadtree_knn_prepared(ix, n_q, nullptr, 0, prune_k, keys, cand, s);
+    FT_HIP(hipEventRecord(ix->ev_p[1], s));
+    // the candidate docs come from the select over the docs' own range: no check
+    flowtree_knn_prepared(ix, n_q, cand, prune_k, k, FT_BATCHED, out_cost, out_doc, s);
+    FT_HIP(hipEventRecord(ix->ev_p[2], s));
+    // the one read of the validation and kernel flags of the whole pipeline
+    uint32_t flags = read_and_clear_status(ix, s);
+    FT_REQUIRE(flags == 0, FT_EHIP, "pipeline kernel reported:" + describe_flags(flags));
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, ix->ev_p[0], ix->ev_p[1]) == hipSuccess) ix->last_pipe_ms[0] = ms;
+    if (hipEventElapsedTime(&ms, ix->ev_p[1], ix->ev_p[2]) == hipSuccess) ix->last_pipe_ms[1] = ms;
+    if (hipEventElapsedTime(&ms, ix->ev_t0, ix->ev_t1) == hipSuccess) ix->last_batched_ms = ms;
+  });
+}
+
+extern "C" ft_status ft_last_pipeline_stats(const ft_index* ix, double* prune_ms, double* rerank_ms) {
+  return guarded([&] {
+    FT_REQUIRE(ix, FT_EINVAL, "NULL index");
+    if (prune_ms) *prune_ms = ix->last_pipe_ms[0];
+    if (rerank_ms) *rerank_ms = ix->last_pipe_ms[1];
   });
 }
 
@@ -636,7 +685,7 @@ extern "C" ft_status ft_flowtree_knn_noalloc(ft_index* ix, const int64_t* q_off,
     a.stride = ix->dp;
     a.status = status;
     a.cost = cost;
-    const int G = lanes_for(ix->dp / 4);
+    const int G = knn_lanes(ix->dp);
     for (int cls = 0; cls <= top_cls; ++cls) {
       with_class(cls, [&](auto cc, auto ww) {
         with_lanes(G, [&](auto gg) {

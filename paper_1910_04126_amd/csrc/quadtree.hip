@@ -636,6 +636,143 @@ static void prepare_postings(ft_index* ix, hipStream_t s) {
 
 using namespace ft;
 
+namespace ft {
+
+// ft_quadtree_knn after its argument checks, on the prepared queries
+// (ix->qry, with embedding) and checked candidate lists.
+void quadtree_knn_prepared(ft_index* ix, int64_t n_q, const int64_t* cand, int32_t n_cand, int32_t k,
+                           uint64_t* out_key, int64_t* out_doc, hipStream_t s) {
+  const int64_t n_cols = cand ? (int64_t)n_cand : ix->docs.n;
+  // the per-query cell counts size the candidate-list tables (all docs: not
+  // needed, and not read back)
+  std::vector<int64_t> eoff(n_q + 1);
+  if (cand) {
+    FT_HIP(hipMemcpyAsync(eoff.data(), ix->qry.ecnt.p, (n_q + 1) * 8, hipMemcpyDeviceToHost, s));
+    FT_HIP(hipStreamSynchronize(s));
+    for (int64_t q = 0; q < n_q; ++q)
+      FT_REQUIRE(eoff[q + 1] - eoff[q] <= SLOTS_LARGE / 2, FT_ERANGE,
+                 "with candidate lists, a query may touch at most 4096 tree cells");
+  }
+  // query chunks bound the key buffer to about 8 GiB (two of them: 16 GiB
+  // of the 288 GB of HBM); two chunks of 2048 queries over 1M docs beat
+  // four of 1024 and eight of 512 (fewer launches, one select tail)
+  const bool compact = !cand && post_narrow(ix->Q, ix->height) && post_compact(ix->Q, ix->height);
+  const int64_t key_bytes = compact ? 4 : 8;
+  const int64_t rows_per_chunk =
+      std::max<int64_t>(1, std::min<int64_t>(n_q, (int64_t(1) << 33) / key_bytes / n_cols));
+  // Ranking all docs in several chunks runs each chunk's select on the
+  // internal stream while the next chunk is ranked (they are bound by
+  // different units), with two key buffers in turn.
+  const bool pipe = !cand && rows_per_chunk < n_q;
+  const int64_t chunk_bytes = (rows_per_chunk * n_cols * key_bytes + 255) & ~int64_t(255);
+  char* key_base = (char*)ix->ws_keys.ensure(chunk_bytes * (pipe ? 2 : 1));
+  uint64_t* keys = (uint64_t*)key_base;
+  uint32_t* ckey_tmp = compact ? (uint32_t*)ix->ws_tiles.ensure(rows_per_chunk * k * 4) : nullptr;
+  if (!cand) prepare_postings(ix, s);
+  hipStream_t s_sel = pipe ? ix->work : s;
+  if (pipe) {
+    FT_HIP(hipEventRecord(ix->ev_a, s));
+    FT_HIP(hipStreamWaitEvent(s_sel, ix->ev_a, 0));
+  }
+  unsigned long long* minmax_base =
+      cand ? nullptr : (unsigned long long*)ix->ws_sel.ensure(rows_per_chunk * 16 * (pipe ? 2 : 1));
+  // the per-row key ranges start empty; with several chunks, the select
+  // stream empties a buffer again right after its select has read it, so
+  // no clearing kernel waits for a CU between two ranking launches
+  if (minmax_base) {
+    const int64_t mm_rows = rows_per_chunk * (pipe ? 2 : 1);
+    k_minmax_init<<<(unsigned)ceil_div(mm_rows, 256), 256, 0, s>>>(minmax_base, mm_rows);
+    FT_HIP(hipGetLastError());
+  }
+  // rows whose sampled select falls back to the exact path, counted
+  uint32_t* sel_exact = (uint32_t*)ix->sel_exact.ensure(4);
+  k_zero_u32<<<1, 1, 0, s>>>(sel_exact);
+  FT_HIP(hipGetLastError());
+  const int64_t n_chunks = ceil_div(n_q, rows_per_chunk);
+  int64_t chunk = 0;
+  for (int64_t r0 = 0; r0 < n_q; r0 += rows_per_chunk, ++chunk) {
+    const int64_t r1 = std::min(n_q, r0 + rows_per_chunk);
+    const int b = pipe ? (int)(chunk & 1) : 0;
+    keys = (uint64_t*)(key_base + b * chunk_bytes);
+    unsigned long long* minmax = nullptr;  // per-row key range, when the ranking kernel gives it
+    if (!cand) {
+      // all docs: the inverted lists, one workgroup per (query, slice)
+      const int64_t rows = r1 - r0, groups = ceil_div(ix->post_nsl, 8);
+      FT_REQUIRE(groups * 8 * rows < (int64_t(1) << 31), FT_ERANGE, "too many (query, slice) workgroups");
+      minmax = minmax_base + b * rows_per_chunk * 2;
+      // the buffers of chunk - 2 must have been read by its select (and
+      // the key ranges emptied again)
+      if (pipe && chunk >= 2) FT_HIP(hipStreamWaitEvent(s, ix->ev_sel[b], 0));
+      auto go = [&](auto narrow, auto packed, auto head) {
+        k_qt_post<decltype(narrow)::value, decltype(packed)::value, decltype(head)::value>
+            <<<(unsigned)(groups * 8 * rows), QP_THREADS, 0, s>>>(
+            ix->post.as<uint16_t>(),
+            (const uint32_t*)((const char*)ix->post.p + ((std::max<int64_t>(1, ix->docs.emb_nnz) * 2 + 15) & ~int64_t(15))),
+            ix->post_dir.as<uint32_t>(), ix->post_cbase.as<uint32_t>(), ix->post_head.as<uint32_t>(),
+            ix->post_hcell.as<uint8_t>(), ix->post_nhead, ix->post_cells,
+            ix->post_slice, ix->post_nsl, ix->docs.ecnt.as<int64_t>(), ix->docs.S.as<uint64_t>(), n_cols,
+            ix->qry.ecnt.as<int64_t>(), ix->qry.ekey.as<uint32_t>(), ix->qry.emass.as<uint32_t>(),
+            ix->qry.S.as<uint64_t>(), r0, rows, ix->B, ix->height, keys, minmax);
+      };
+      const bool head = ix->post_nhead > 0;
+      if (compact && head) go(std::true_type{}, std::true_type{}, std::true_type{});
+      else if (compact) go(std::true_type{}, std::true_type{}, std::false_type{});
+      else if (post_narrow(ix->Q, ix->height) && head) go(std::true_type{}, std::false_type{}, std::true_type{});
+      else if (post_narrow(ix->Q, ix->height)) go(std::true_type{}, std::false_type{}, std::false_type{});
+      else go(std::false_type{}, std::false_type{}, std::false_type{});
+      FT_HIP(hipGetLastError());
+    } else {
+      // candidate lists: one query per workgroup, its table in LDS
+      std::vector<QtTile> tiles;
+      int64_t big = 0;
+      for (int64_t q = r0; q < r1; ++q) {
+        int64_t ne = eoff[q + 1] - eoff[q];
+        int l = 1;
+        while ((1ll << l) < 2 * ne) ++l;
+        tiles.push_back(QtTile{(int32_t)q, 1, l, 0});
+        big = std::max<int64_t>(big, 1ll << l);
+      }
+      QtTile* dt = (QtTile*)ix->ws_tiles.ensure(tiles.size() * sizeof(QtTile));
+      FT_HIP(hipMemcpyAsync(dt, tiles.data(), tiles.size() * sizeof(QtTile), hipMemcpyHostToDevice, s));
+      dim3 grid((unsigned)tiles.size(), 1);
+      if (big <= SLOTS_SMALL)
+        k_qt_tile<SLOTS_SMALL><<<grid, QT_THREADS, 0, s>>>(
+            dt, ix->qry.ecnt.as<int64_t>(), ix->qry.ekey.as<uint32_t>(), ix->qry.emass.as<uint32_t>(),
+            ix->qry.S.as<uint64_t>(), ix->docs.ecnt.as<int64_t>(), ix->docs.ekey.as<uint32_t>(),
+            ix->docs.emass.as<uint32_t>(), ix->docs.S.as<uint64_t>(), cand, n_cols, n_cols, ix->B, r0, keys);
+      else
+        k_qt_tile<SLOTS_LARGE><<<grid, QT_THREADS, 0, s>>>(
+            dt, ix->qry.ecnt.as<int64_t>(), ix->qry.ekey.as<uint32_t>(), ix->qry.emass.as<uint32_t>(),
+            ix->qry.S.as<uint64_t>(), ix->docs.ecnt.as<int64_t>(), ix->docs.ekey.as<uint32_t>(),
+            ix->docs.emass.as<uint32_t>(), ix->docs.S.as<uint64_t>(), cand, n_cols, n_cols, ix->B, r0, keys);
+      FT_HIP(hipGetLastError());
+      FT_HIP(hipStreamSynchronize(s));  // the tile table is reused by the next chunk
+    }
+    if (pipe) {
+      FT_HIP(hipEventRecord(ix->ev_rank[b], s));
+      FT_HIP(hipStreamWaitEvent(s_sel, ix->ev_rank[b], 0));
+    }
+    if (compact)
+      topk_rows(reinterpret_cast<const uint32_t*>(keys), r1 - r0, n_cols, nullptr, k, out_key + r0 * k,
+                ix->B - ix->height, out_doc + r0 * k, ckey_tmp, s_sel, reinterpret_cast<const uint64_t*>(minmax),
+                sel_exact);
+    else
+      topk_rows(keys, r1 - r0, n_cols, cand ? cand + r0 * n_cols : nullptr, k, out_key + r0 * k, out_doc + r0 * k,
+                s_sel, reinterpret_cast<const uint64_t*>(minmax), sel_exact);
+    if (minmax && pipe && chunk + 2 < n_chunks) {
+      k_minmax_init<<<(unsigned)ceil_div(rows_per_chunk, 256), 256, 0, s_sel>>>(minmax, rows_per_chunk);
+      FT_HIP(hipGetLastError());
+    }
+    if (pipe) FT_HIP(hipEventRecord(ix->ev_sel[b], s_sel));
+  }
+  if (pipe) {
+    FT_HIP(hipEventRecord(ix->ev_b, s_sel));
+    FT_HIP(hipStreamWaitEvent(s, ix->ev_b, 0));
+  }
+}
+
+}  // namespace ft
+
 extern "C" ft_status ft_quadtree_knn(ft_index* ix, const int64_t* q_off, const uint32_t* q_id, const uint32_t* q_mass,
                                      int64_t n_q, const int64_t* cand, int32_t n_cand, int32_t k, uint64_t* out_key,
                                      int64_t* out_doc, void* stream) {
@@ -649,129 +786,7 @@ extern "C" ft_status ft_quadtree_knn(ft_index* ix, const int64_t* q_off, const u
     FT_REQUIRE(cand || n_cols <= 4096 || k <= 1024, FT_ERANGE, "k > 1024 needs at most 4096 candidates");
     prepare_dists(ix, ix->qry, q_off, q_id, q_mass, n_q, true, s, "queries");
     if (cand) check_indices(ix, cand, n_q * n_cand, ix->docs.n, s, "cand");
-    std::vector<int64_t> eoff(n_q + 1);
-    FT_HIP(hipMemcpyAsync(eoff.data(), ix->qry.ecnt.p, (n_q + 1) * 8, hipMemcpyDeviceToHost, s));
-    FT_HIP(hipStreamSynchronize(s));
-    if (cand)
-      for (int64_t q = 0; q < n_q; ++q)
-        FT_REQUIRE(eoff[q + 1] - eoff[q] <= SLOTS_LARGE / 2, FT_ERANGE,
-                   "with candidate lists, a query may touch at most 4096 tree cells");
-    // query chunks bound the key buffer to about 8 GiB (two of them: 16 GiB
-    // of the 288 GB of HBM); two chunks of 2048 queries over 1M docs beat
-    // four of 1024 and eight of 512 (fewer launches, one select tail)
-    const bool compact = !cand && post_narrow(ix->Q, ix->height) && post_compact(ix->Q, ix->height);
-    const int64_t key_bytes = compact ? 4 : 8;
-    const int64_t rows_per_chunk =
-        std::max<int64_t>(1, std::min<int64_t>(n_q, (int64_t(1) << 33) / key_bytes / n_cols));
-    // Ranking all docs in several chunks runs each chunk's select on the
-    // internal stream while the next chunk is ranked (they are bound by
-    // different units), with two key buffers in turn.
-    const bool pipe = !cand && rows_per_chunk < n_q;
-    const int64_t chunk_bytes = (rows_per_chunk * n_cols * key_bytes + 255) & ~int64_t(255);
-    char* key_base = (char*)ix->ws_keys.ensure(chunk_bytes * (pipe ? 2 : 1));
-    uint64_t* keys = (uint64_t*)key_base;
-    uint32_t* ckey_tmp = compact ? (uint32_t*)ix->ws_tiles.ensure(rows_per_chunk * k * 4) : nullptr;
-    if (!cand) prepare_postings(ix, s);
-    hipStream_t s_sel = pipe ? ix->work : s;
-    if (pipe) {
-      FT_HIP(hipEventRecord(ix->ev_a, s));
-      FT_HIP(hipStreamWaitEvent(s_sel, ix->ev_a, 0));
-    }
-    unsigned long long* minmax_base =
-        cand ? nullptr : (unsigned long long*)ix->ws_sel.ensure(rows_per_chunk * 16 * (pipe ? 2 : 1));
-    // the per-row key ranges start empty; with several chunks, the select
-    // stream empties a buffer again right after its select has read it, so
-    // no clearing kernel waits for a CU between two ranking launches
-    if (minmax_base) {
-      const int64_t mm_rows = rows_per_chunk * (pipe ? 2 : 1);
-      k_minmax_init<<<(unsigned)ceil_div(mm_rows, 256), 256, 0, s>>>(minmax_base, mm_rows);
-      FT_HIP(hipGetLastError());
-    }
-    // rows whose sampled select falls back to the exact path, counted
-    uint32_t* sel_exact = (uint32_t*)ix->sel_exact.ensure(4);
-    k_zero_u32<<<1, 1, 0, s>>>(sel_exact);
-    FT_HIP(hipGetLastError());
-    const int64_t n_chunks = ceil_div(n_q, rows_per_chunk);
-    int64_t chunk = 0;
-    for (int64_t r0 = 0; r0 < n_q; r0 += rows_per_chunk, ++chunk) {
-      const int64_t r1 = std::min(n_q, r0 + rows_per_chunk);
-      const int b = pipe ? (int)(chunk & 1) : 0;
-      keys = (uint64_t*)(key_base + b * chunk_bytes);
-      unsigned long long* minmax = nullptr;  // per-row key range, when the ranking kernel gives it
-      if (!cand) {
-        // all docs: the inverted lists, one workgroup per (query, slice)
-        const int64_t rows = r1 - r0, groups = ceil_div(ix->post_nsl, 8);
-        FT_REQUIRE(groups * 8 * rows < (int64_t(1) << 31), FT_ERANGE, "too many (query, slice) workgroups");
-        minmax = minmax_base + b * rows_per_chunk * 2;
-        // the buffers of chunk - 2 must have been read by its select (and
-        // the key ranges emptied again)
-        if (pipe && chunk >= 2) FT_HIP(hipStreamWaitEvent(s, ix->ev_sel[b], 0));
-        auto go = [&](auto narrow, auto packed, auto head) {
-          k_qt_post<decltype(narrow)::value, decltype(packed)::value, decltype(head)::value>
-              <<<(unsigned)(groups * 8 * rows), QP_THREADS, 0, s>>>(
-              ix->post.as<uint16_t>(),
-              (const uint32_t*)((const char*)ix->post.p + ((std::max<int64_t>(1, ix->docs.emb_nnz) * 2 + 15) & ~int64_t(15))),
-              ix->post_dir.as<uint32_t>(), ix->post_cbase.as<uint32_t>(), ix->post_head.as<uint32_t>(),
-              ix->post_hcell.as<uint8_t>(), ix->post_nhead, ix->post_cells,
-              ix->post_slice, ix->post_nsl, ix->docs.ecnt.as<int64_t>(), ix->docs.S.as<uint64_t>(), n_cols,
-              ix->qry.ecnt.as<int64_t>(), ix->qry.ekey.as<uint32_t>(), ix->qry.emass.as<uint32_t>(),
-              ix->qry.S.as<uint64_t>(), r0, rows, ix->B, ix->height, keys, minmax);
-        };
-        const bool head = ix->post_nhead > 0;
-        if (compact && head) go(std::true_type{}, std::true_type{}, std::true_type{});
-        else if (compact) go(std::true_type{}, std::true_type{}, std::false_type{});
-        else if (post_narrow(ix->Q, ix->height) && head) go(std::true_type{}, std::false_type{}, std::true_type{});
-        else if (post_narrow(ix->Q, ix->height)) go(std::true_type{}, std::false_type{}, std::false_type{});
-        else go(std::false_type{}, std::false_type{}, std::false_type{});
-        FT_HIP(hipGetLastError());
-      } else {
-        // candidate lists: one query per workgroup, its table in LDS
-        std::vector<QtTile> tiles;
-        int64_t big = 0;
-        for (int64_t q = r0; q < r1; ++q) {
-          int64_t ne = eoff[q + 1] - eoff[q];
-          int l = 1;
-          while ((1ll << l) < 2 * ne) ++l;
-          tiles.push_back(QtTile{(int32_t)q, 1, l, 0});
-          big = std::max<int64_t>(big, 1ll << l);
-        }
-        QtTile* dt = (QtTile*)ix->ws_tiles.ensure(tiles.size() * sizeof(QtTile));
-        FT_HIP(hipMemcpyAsync(dt, tiles.data(), tiles.size() * sizeof(QtTile), hipMemcpyHostToDevice, s));
-        dim3 grid((unsigned)tiles.size(), 1);
-        if (big <= SLOTS_SMALL)
-          k_qt_tile<SLOTS_SMALL><<<grid, QT_THREADS, 0, s>>>(
-              dt, ix->qry.ecnt.as<int64_t>(), ix->qry.ekey.as<uint32_t>(), ix->qry.emass.as<uint32_t>(),
-              ix->qry.S.as<uint64_t>(), ix->docs.ecnt.as<int64_t>(), ix->docs.ekey.as<uint32_t>(),
-              ix->docs.emass.as<uint32_t>(), ix->docs.S.as<uint64_t>(), cand, n_cols, n_cols, ix->B, r0, keys);
-        else
-          k_qt_tile<SLOTS_LARGE><<<grid, QT_THREADS, 0, s>>>(
-              dt, ix->qry.ecnt.as<int64_t>(), ix->qry.ekey.as<uint32_t>(), ix->qry.emass.as<uint32_t>(),
-              ix->qry.S.as<uint64_t>(), ix->docs.ecnt.as<int64_t>(), ix->docs.ekey.as<uint32_t>(),
-              ix->docs.emass.as<uint32_t>(), ix->docs.S.as<uint64_t>(), cand, n_cols, n_cols, ix->B, r0, keys);
-        FT_HIP(hipGetLastError());
-        FT_HIP(hipStreamSynchronize(s));  // the tile table is reused by the next chunk
-      }
-      if (pipe) {
-        FT_HIP(hipEventRecord(ix->ev_rank[b], s));
-        FT_HIP(hipStreamWaitEvent(s_sel, ix->ev_rank[b], 0));
-      }
-      if (compact)
-        topk_rows(reinterpret_cast<const uint32_t*>(keys), r1 - r0, n_cols, nullptr, k, out_key + r0 * k,
-                  ix->B - ix->height, out_doc + r0 * k, ckey_tmp, s_sel, reinterpret_cast<const uint64_t*>(minmax),
-                  sel_exact);
-      else
-        topk_rows(keys, r1 - r0, n_cols, cand ? cand + r0 * n_cols : nullptr, k, out_key + r0 * k, out_doc + r0 * k,
-                  s_sel, reinterpret_cast<const uint64_t*>(minmax), sel_exact);
-      if (minmax && pipe && chunk + 2 < n_chunks) {
-        k_minmax_init<<<(unsigned)ceil_div(rows_per_chunk, 256), 256, 0, s_sel>>>(minmax, rows_per_chunk);
-        FT_HIP(hipGetLastError());
-      }
-      if (pipe) FT_HIP(hipEventRecord(ix->ev_sel[b], s_sel));
-    }
-    if (pipe) {
-      FT_HIP(hipEventRecord(ix->ev_b, s_sel));
-      FT_HIP(hipStreamWaitEvent(s, ix->ev_b, 0));
-    }
+    quadtree_knn_prepared(ix, n_q, cand, n_cand, k, out_key, out_doc, s);
   });
 }
 

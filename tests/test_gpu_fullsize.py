@@ -34,12 +34,17 @@ def say(*a):
 
 def pipeline_check(ft, ds, prune, k, sample, n_flow_pairs=120):
     """Prune all queries over all docs, rerank the candidates (batched), and
-    check the sampled queries against the oracle."""
+    check the sampled queries against the oracle; the one-call pipeline must
+    give the same output bit for bit."""
     ix = build_index(ft, ds)
     qo, qi, qm = queries(ds)
     keys, cand = ft.quadtree_knn(ix, qo, qi, qm, prune)
     costs, docs = ft.flowtree_knn(ix, qo, qi, qm, k, cand=cand, mode=ft.FT_BATCHED)
+    say("  the same search in one knn_pipeline call")
+    p_costs, p_docs = ft.knn_pipeline(ix, qo, qi, qm, prune, k)
     torch.cuda.synchronize()
+    assert torch.equal(p_docs, docs)
+    assert torch.equal(p_costs.view(torch.int32), costs.view(torch.int32))
     keys, cand = keys.cpu().numpy().view(np.uint64), cand.cpu().numpy()
     costs, docs = costs.cpu().numpy(), docs.cpu().numpy()
     T = oracle_tree(ds)
