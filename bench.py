@@ -48,10 +48,10 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 # rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a 1 GiB copy
 # (profiles/flowtree_quadtree_batched_hbm_traffic.md), valid while the kernel
 # sources hash to TRAFFIC_SOURCES_SHA1.
-TRAFFIC_BYTES = {"batched": 2.7498e+11, "batched_v1m": 4.1620e+11}
+TRAFFIC_BYTES = {"batched": 2.7460e+11, "batched_v1m": 4.1235e+11}
 TRAFFIC_SOURCES = ("paper_1910_04126_amd/csrc/flow.h", "paper_1910_04126_amd/csrc/flowtree.hip",
                    "paper_1910_04126_amd/csrc/wave.h", "paper_1910_04126_amd/csrc/common.h")
-TRAFFIC_SOURCES_SHA1 = "48234b915ae1701a2fc8657d04b0344662588139"
+TRAFFIC_SOURCES_SHA1 = "02f4b1c043802d75c3e84f280a421598430db68c"
 
 
 def measured_traffic(workload):
@@ -66,13 +66,14 @@ def measured_traffic(workload):
 # step: k_qt_post ranks, k_topk_window selects), from rocprofv3 --pmc runs
 # (profiles/quadtree_prune_batched_counters.md), valid while the prune
 # sources hash to PRUNE_SOURCES_SHA1: HBM bytes per step (FETCH_SIZE and
-# WRITE_SIZE scaled by the 1 GiB copy), and the ranking kernel's LDS busy
-# share of cycles, bank-conflict share of LDS cycles, VALU issue share and
-# L2 hit rate.
-PRUNE_COUNTERS = {}
+# WRITE_SIZE scaled by the 1 GiB copy), and the ranking kernel's LDS active
+# share of cycles, bank-conflict share of LDS cycles, VALU issue against the
+# 1.7 per CU-cycle that a VALU-only probe reaches, and L2 hit rate.
+PRUNE_COUNTERS = {"batched": {"bytes": 8.7930e+10, "lds_busy": 0.40, "lds_bank_conflict": 0.42,
+                              "valu_issue": 0.45, "l2_hit": 0.86}}
 PRUNE_SOURCES = ("paper_1910_04126_amd/csrc/quadtree.hip", "paper_1910_04126_amd/csrc/select.hip",
                  "paper_1910_04126_amd/csrc/wave.h", "paper_1910_04126_amd/csrc/common.h")
-PRUNE_SOURCES_SHA1 = ""
+PRUNE_SOURCES_SHA1 = "75166dfda33ba041dc15d5c5c1cefb5d83ffa3ad"
 
 
 def _sources_sha1(files):
