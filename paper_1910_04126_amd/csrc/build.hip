@@ -562,7 +562,7 @@ extern "C" const char* ft_last_error(void) { return ft::g_last_error.c_str(); }
 extern "C" void ft_free(ft_index* ix) {
   if (!ix) return;
   ix->graphs.reset();
-  for (DevBuf* b : {&ix->post, &ix->post_dir, &ix->post_cbase, &ix->post_head, &ix->post_hcell, &ix->ws_pipe, &ix->Xm, &ix->Xn, &ix->perm, &ix->inv, &ix->st, &ix->leafd, &ix->anc, &ix->status, &ix->ws_keys,
+  for (DevBuf* b : {&ix->post, &ix->post_dir, &ix->post_cbase, &ix->post_head, &ix->post_hcell, &ix->post_s32, &ix->ws_pipe, &ix->Xm, &ix->Xn, &ix->perm, &ix->inv, &ix->st, &ix->leafd, &ix->anc, &ix->status, &ix->ws_keys,
                     &ix->ws_cost, &ix->ws_tiles, &ix->ws_lists, &ix->ws_counts, &ix->ws_misc, &ix->ws_sel, &ix->ws_rerank,
                     &ix->ws_gx64, &ix->ws_adj, &ix->ws_glist, &ix->sel_exact,
                     &ix->fwd_id, &ix->fwd_eta, &ix->fwd_key, &ix->fwd_bind, &ix->fwd_cnt, &ix->fwd_base, &ix->fwd_sig})

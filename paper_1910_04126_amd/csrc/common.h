@@ -140,6 +140,7 @@ struct ft_index {
   ft::DevBuf post_dir;     // u32 [post_nsl * post_cells] end offset of each cell's list in its slice
   ft::DevBuf post_cbase;   // u32 [32] first cell number of each depth
   ft::DevBuf post_head;     // u32 [post_nsl][post_nhead][post_slice] dense cell masses of the head cells, by doc
+  ft::DevBuf post_s32;      // u32 [docs] S_d in compact key units (when the keys are compact)
   ft::DevBuf post_hcell;    // u8 [post_cells] head index of each cell (0xFF: a listed cell)
   int64_t post_slice = 0, post_cells = 0, post_nsl = 0;
   int32_t post_nhead = 0;

@@ -174,20 +174,20 @@ __device__ int flow_match(FlowLds<C, W>& L, const int nq, const int nd, const ui
     const int k = 31 - __clz(mask);
     mask &= ~(1u << k);
     // local segmented sums of this lane's items
+    // (items past n are neutral: no mass, and each starts and ends its own
+    // segment after every real one, so no test of t < n is needed)
     uint32_t run_p = 0, run_n = 0;
     int last_start = -1, first_end = 0x7FFFFFFF;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       const int t = t0 + c;
-      if (t < n) {
-        if ((c ? lcn[c - 1] : lcn_prev) < k) {
-          run_p = run_n = 0;
-          last_start = t;
-        }
-        if (isq[c]) run_n += res[c];
-        else run_p += res[c];
-        if (lcn[c] < k && first_end == 0x7FFFFFFF) first_end = t;
+      if ((c ? lcn[c - 1] : lcn_prev) < k) {
+        run_p = run_n = 0;
+        last_start = t;
       }
+      if (isq[c]) run_n += res[c];
+      else run_p += res[c];
+      if (lcn[c] < k && first_end == 0x7FFFFFFF) first_end = t;
     }
     uint32_t tp = run_p, tn = run_n;
     const bool has = wave_seg_incl_sum2(tp, tn, last_start >= 0);
@@ -240,27 +240,23 @@ __device__ int flow_match(FlowLds<C, W>& L, const int nq, const int nd, const ui
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       const int t = t0 + c;
-      hi[c] = 0u;
-      a0[c] = 0;
-      if (t < n) {
-        if ((c ? lcn[c - 1] : lcn_prev) < k) {
-          run_p = run_n = 0;
-          s0 = t;
-        }
-        if (isq[c]) run_n += res[c];
-        else run_p += res[c];
-        L.pp[t] = run_p;
-        L.pn[t] = run_n;
-        hi[c] = isq[c] ? run_n : run_p;
-        a0[c] = s0;
+      if ((c ? lcn[c - 1] : lcn_prev) < k) {
+        run_p = run_n = 0;
+        s0 = t;
       }
+      if (isq[c]) run_n += res[c];
+      else run_p += res[c];
+      L.pp[t] = run_p;  // t < N always; past n the values are never read
+      L.pn[t] = run_n;
+      hi[c] = isq[c] ? run_n : run_p;
+      a0[c] = s0;
     }
     {
       int e = next_end;
 #pragma unroll
       for (int c = C - 1; c >= 0; --c) {
         if (lcn[c] < k) e = t0 + c;
-        e0[c] = t0 + c < n ? e : 0;
+        e0[c] = e;
       }
     }
     __syncthreads();
@@ -277,7 +273,7 @@ __device__ int flow_match(FlowLds<C, W>& L, const int nq, const int nd, const ui
       const uint32_t Tp = L.pp[e0[c]], Tn = L.pn[e0[c]];
       M[c] = Tp < Tn ? Tp : Tn;
       lo[c] = hi[c] - res[c];
-      want[c] = t0 + c < n && res[c] > 0u && lo[c] < M[c];
+      want[c] = res[c] > 0u && lo[c] < M[c];
       base[c] = a0[c];
       len[c] = want[c] ? e0[c] - a0[c] + 1 : 1;
     }
@@ -337,7 +333,7 @@ __device__ int flow_match(FlowLds<C, W>& L, const int nq, const int nd, const ui
           }
           ++cnt;
         }
-        if (t0 + c < n && res[c] > 0u) res[c] = hi[c] > M[c] ? hi[c] - (lo[c] > M[c] ? lo[c] : M[c]) : 0u;
+        if (res[c] > 0u) res[c] = hi[c] > M[c] ? hi[c] - (lo[c] > M[c] ? lo[c] : M[c]) : 0u;
       }
     }
     const int incl = wave_incl_sum(cnt);
@@ -379,7 +375,7 @@ __device__ int flow_match(FlowLds<C, W>& L, const int nq, const int nd, const ui
   bool left = false;
 #pragma unroll
   for (int c = 0; c < C; ++c)
-    if (t0 + c < n && res[c] != 0u) left = true;
+    if (res[c] != 0u) left = true;
   if (__ballot(left) && lane == 0) atomicOr(status, ERR_FLOW);
   return E;
 }

@@ -247,6 +247,12 @@ __global__ __launch_bounds__(64) void k_post_fill(const int64_t* __restrict__ eo
   }
 }
 
+// S_d in units of 2^up (a multiple of it when keys are compact), as u32.
+__global__ void k_s32(const uint64_t* __restrict__ S, int64_t n, int up, uint32_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (uint32_t)(S[i] >> up);
+}
+
 // Wavefront per doc: its masses in the head cells, into the dense rows of
 // its slice (rows start zeroed).
 __global__ __launch_bounds__(64) void k_head_fill(const int64_t* __restrict__ eoff, const uint32_t* __restrict__ ekey,
@@ -275,7 +281,7 @@ __global__ __launch_bounds__(QP_THREADS) __attribute__((amdgpu_num_sgpr(72))) vo
     const uint32_t* __restrict__ cbase, const uint32_t* __restrict__ head_rows, const uint8_t* __restrict__ hcell,
     int nhead,
     int64_t n_cells, int64_t S, int64_t n_sl, const int64_t* __restrict__ d_eoff, const uint64_t* __restrict__ d_S,
-    int64_t n_docs, const int64_t* __restrict__ q_eoff, const uint32_t* __restrict__ q_ekey,
+    const uint32_t* __restrict__ d_S32, int64_t n_docs, const int64_t* __restrict__ q_eoff, const uint32_t* __restrict__ q_ekey,
     const uint32_t* __restrict__ q_emass, const uint64_t* __restrict__ q_S, int64_t r0, int64_t n_rows, int B, int H,
     void* __restrict__ keys_out, unsigned long long* __restrict__ minmax) {
   static_assert(NARROW || !COMPACT, "compact keys need narrow counters");
@@ -384,36 +390,60 @@ __global__ __launch_bounds__(QP_THREADS) __attribute__((amdgpu_num_sgpr(72))) vo
       for (uint32_t j = 0; j < np; ++j) pitem[p0 + j] = (uint8_t)i;
     }
     __syncthreads();
+    // a piece belongs to one wavefront, so its list offset, length, query
+    // mass and shift are scalars; the entries are read at 32-bit byte offsets
+    // from the slice's list base, and a full piece (every piece of a list but
+    // its last) needs no per-lane bound
+    const char* pd_base = reinterpret_cast<const char*>(Pd);
+    const char* pm_base = reinterpret_cast<const char*>(Pm);
     for (uint32_t p0 = w * QP_U; p0 < n_pieces; p0 += QP_WAVES * QP_U) {
       uint32_t ed[QP_U][QP_PIECE / 64], em[QP_U][QP_PIECE / 64];
       uint32_t am[QP_U], sh[QP_U], cnt[QP_U];
 #pragma unroll
       for (int u = 0; u < QP_U; ++u) {
         const uint32_t p = p0 + u;
-        cnt[u] = 0;
-        am[u] = sh[u] = 0;
-        uint32_t at = 0;
+        uint32_t c = 0, a = 0, s = 0, at = 0;
         if (p < n_pieces) {
           const uint32_t it = pitem[p];
           const uint4 item = items[it];
           const uint32_t off = (p - pstart[it]) * QP_PIECE;
-          cnt[u] = min((uint32_t)QP_PIECE, item.y - off);
-          am[u] = item.z;
-          sh[u] = item.w;
+          c = min((uint32_t)QP_PIECE, item.y - off);
+          a = item.z;
+          s = item.w;
           at = item.x + off;
         }
+        cnt[u] = __builtin_amdgcn_readfirstlane(c);
+        am[u] = __builtin_amdgcn_readfirstlane(a);
+        sh[u] = __builtin_amdgcn_readfirstlane(s);
+        at = __builtin_amdgcn_readfirstlane(at);
+        if (cnt[u] == (uint32_t)QP_PIECE) {
+          const char* pd_lane = pd_base + 2u * (at + lane);
+          const char* pm_lane = pm_base + 4u * (at + lane);
 #pragma unroll
-        for (int j = 0; j < QP_PIECE / 64; ++j) {
-          const uint32_t x = j * 64 + lane;
-          ed[u][j] = x < cnt[u] ? (uint32_t)Pd[at + x] : 0u;
-          em[u][j] = x < cnt[u] ? Pm[at + x] : 0u;
+          for (int j = 0; j < QP_PIECE / 64; ++j) {
+            ed[u][j] = *reinterpret_cast<const uint16_t*>(pd_lane + 128 * j);
+            em[u][j] = *reinterpret_cast<const uint32_t*>(pm_lane + 256 * j);
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < QP_PIECE / 64; ++j) {
+            const uint32_t x = j * 64 + lane;
+            ed[u][j] = x < cnt[u] ? (uint32_t)*reinterpret_cast<const uint16_t*>(pd_base + 2u * (at + x)) : 0u;
+            em[u][j] = x < cnt[u] ? *reinterpret_cast<const uint32_t*>(pm_base + 4u * (at + x)) : 0u;
+          }
         }
       }
 #pragma unroll
-      for (int u = 0; u < QP_U; ++u)
+      for (int u = 0; u < QP_U; ++u) {
+        if (cnt[u] == (uint32_t)QP_PIECE) {
 #pragma unroll
-        for (int j = 0; j < QP_PIECE / 64; ++j)
-          if ((uint32_t)(j * 64 + lane) < cnt[u]) atomicAdd(&acc[ed[u][j]], (Acc)min(am[u], em[u][j]) << sh[u]);
+          for (int j = 0; j < QP_PIECE / 64; ++j) atomicAdd(&acc[ed[u][j]], (Acc)min(am[u], em[u][j]) << sh[u]);
+        } else {
+#pragma unroll
+          for (int j = 0; j < QP_PIECE / 64; ++j)
+            if ((uint32_t)(j * 64 + lane) < cnt[u]) atomicAdd(&acc[ed[u][j]], (Acc)min(am[u], em[u][j]) << sh[u]);
+        }
+      }
     }
     __syncthreads();
   }
@@ -422,13 +452,27 @@ __global__ __launch_bounds__(QP_THREADS) __attribute__((amdgpu_num_sgpr(72))) vo
   const uint64_t* Sd = d_S + d0;
   const int up = NARROW ? B - H : 0;
   unsigned long long mn = ~0ull, mx = 0ull;
-  for (int i = tid; i < nd; i += QP_THREADS) {
-    // compact: in units of 2^(B - H); S_q and S_d are multiples of it
-    const uint64_t key = COMPACT ? ((Sq + Sd[i]) >> up) - ((uint64_t)acc[i] << 1)
-                                 : Sq + Sd[i] - (((uint64_t)acc[i] << up) << 1);
-    out[i] = (Key)key;
-    mn = key < mn ? key : mn;
-    mx = key > mx ? key : mx;
+  if constexpr (COMPACT) {
+    // in units of 2^(B - H): S_q and S_d are multiples of it, and the key
+    // fits 32 bits
+    const uint32_t sq = (uint32_t)(Sq >> up);
+    const uint32_t* Sd32 = d_S32 + d0;
+    uint32_t mn32 = 0xFFFFFFFFu, mx32 = 0u;
+    for (int i = tid; i < nd; i += QP_THREADS) {
+      const uint32_t key = sq + Sd32[i] - ((uint32_t)acc[i] << 1);
+      out[i] = (Key)key;
+      mn32 = key < mn32 ? key : mn32;
+      mx32 = key > mx32 ? key : mx32;
+    }
+    mn = mn32 == 0xFFFFFFFFu ? ~0ull : (unsigned long long)mn32;
+    mx = mx32;
+  } else {
+    for (int i = tid; i < nd; i += QP_THREADS) {
+      const uint64_t key = Sq + Sd[i] - (((uint64_t)acc[i] << up) << 1);
+      out[i] = (Key)key;
+      mn = key < mn ? key : mn;
+      mx = key > mx ? key : mx;
+    }
   }
   // the row's smallest and largest key, for the selection that follows
 #pragma unroll
@@ -601,6 +645,13 @@ static void prepare_postings(ft_index* ix, hipStream_t s) {
   // head cells: touched by at least half of the docs, the longest
   // first (ties by cell number), at most QP_HEAD_MAX; dense rows only with
   // narrow counters over full 8192-doc slices
+  if (narrow && post_compact(ix->Q, ix->height)) {
+    // compact keys: the docs' S in key units, 4 bytes per doc for the
+    // ranking kernel's last pass instead of 8
+    uint32_t* s32 = (uint32_t*)ix->post_s32.ensure(n * 4);
+    k_s32<<<(unsigned)ceil_div(n, 256), 256, 0, s>>>(ix->docs.S.as<uint64_t>(), n, ix->B - ix->height, s32);
+    FT_HIP(hipGetLastError());
+  }
   ix->post_nhead = 0;
   if (!narrow || S != QP_HEAD_SLICE) return;
   std::vector<uint32_t> hdir(n_sl * n_cells);
@@ -710,7 +761,8 @@ void quadtree_knn_prepared(ft_index* ix, int64_t n_q, const int64_t* cand, int32
             (const uint32_t*)((const char*)ix->post.p + ((std::max<int64_t>(1, ix->docs.emb_nnz) * 2 + 15) & ~int64_t(15))),
             ix->post_dir.as<uint32_t>(), ix->post_cbase.as<uint32_t>(), ix->post_head.as<uint32_t>(),
             ix->post_hcell.as<uint8_t>(), ix->post_nhead, ix->post_cells,
-            ix->post_slice, ix->post_nsl, ix->docs.ecnt.as<int64_t>(), ix->docs.S.as<uint64_t>(), n_cols,
+            ix->post_slice, ix->post_nsl, ix->docs.ecnt.as<int64_t>(), ix->docs.S.as<uint64_t>(),
+            ix->post_s32.as<uint32_t>(), n_cols,
             ix->qry.ecnt.as<int64_t>(), ix->qry.ekey.as<uint32_t>(), ix->qry.emass.as<uint32_t>(),
             ix->qry.S.as<uint64_t>(), r0, rows, ix->B, ix->height, keys, minmax);
       };

@@ -33,7 +33,8 @@ __device__ __forceinline__ uint32_t wave_or(uint32_t v) {
 }
 
 // DPP moves (GFX9 controls): the value of the lane that CTRL selects, or
-// `old` where that lane lies outside the row or the row is off in ROWS.
+// `old` where that lane lies outside the row or the row is off in ROWS (with
+// bound_ctrl off, such a lane's write is disabled and it keeps `old`).
 // row_shr:n is 0x110 + n, row_shl:n 0x100 + n, wave_shr:1 0x138, wave_shl:1
 // 0x130, row_bcast:15 0x142 (lane 15 of a row to the whole next row),
 // row_bcast:31 0x143 (lane 31 to rows 2 and 3).
@@ -71,21 +72,16 @@ __device__ __forceinline__ T lane_value(T v, int l) {
 }
 
 // Inclusive scan over lanes of a 32-bit value under an associative op with
-// identity `id`: rows of 16 by row shifts of 1, 2, 4, 8, then rows 1 and 3
-// take lane 15 of the row before, then rows 2 and 3 take lane 31.  All of it
-// runs on DPP moves in the vector ALU.
+// identity `id`: rows of 16 by row shifts of 1, 2, 4, 8 (a lane with no
+// source that far back in its row takes `id`), then rows 1 and 3 take lane
+// 15 of the row before, then rows 2 and 3 take lane 31.  All of it runs on
+// DPP moves in the vector ALU.
 template <class T, class Op>
 __device__ __forceinline__ T wave_scan32(T v, const T id, Op op) {
-  const int r = lane_id() & 15;
-  T u;
-  u = from32<T>(dpp_u32<0x111>(bits32(id), bits32(v)));
-  if (r >= 1) v = op(v, u);
-  u = from32<T>(dpp_u32<0x112>(bits32(id), bits32(v)));
-  if (r >= 2) v = op(v, u);
-  u = from32<T>(dpp_u32<0x114>(bits32(id), bits32(v)));
-  if (r >= 4) v = op(v, u);
-  u = from32<T>(dpp_u32<0x118>(bits32(id), bits32(v)));
-  if (r >= 8) v = op(v, u);
+  v = op(v, from32<T>(dpp_u32<0x111>(bits32(id), bits32(v))));
+  v = op(v, from32<T>(dpp_u32<0x112>(bits32(id), bits32(v))));
+  v = op(v, from32<T>(dpp_u32<0x114>(bits32(id), bits32(v))));
+  v = op(v, from32<T>(dpp_u32<0x118>(bits32(id), bits32(v))));
   v = op(v, from32<T>(dpp_u32<0x142, 0xA>(bits32(id), bits32(v))));
   v = op(v, from32<T>(dpp_u32<0x143, 0xC>(bits32(id), bits32(v))));
   return v;
@@ -116,17 +112,12 @@ __device__ __forceinline__ int wave_incl_max(int v) {
 // 32-bit signed): row shifts towards lane 0 inside rows of 16, then each row
 // takes the minima of the rows after it, read from their first lanes.
 __device__ __forceinline__ int wave_suffix_min(int v) {
-  const int l = lane_id(), r = l & 15;
+  const int l = lane_id();
   const uint32_t id = 0x7FFFFFFFu;
-  int u;
-  u = (int)dpp_u32<0x101>(id, (uint32_t)v);
-  if (r + 1 <= 15 && u < v) v = u;
-  u = (int)dpp_u32<0x102>(id, (uint32_t)v);
-  if (r + 2 <= 15 && u < v) v = u;
-  u = (int)dpp_u32<0x104>(id, (uint32_t)v);
-  if (r + 4 <= 15 && u < v) v = u;
-  u = (int)dpp_u32<0x108>(id, (uint32_t)v);
-  if (r + 8 <= 15 && u < v) v = u;
+  v = min(v, (int)dpp_u32<0x101>(id, (uint32_t)v));
+  v = min(v, (int)dpp_u32<0x102>(id, (uint32_t)v));
+  v = min(v, (int)dpp_u32<0x104>(id, (uint32_t)v));
+  v = min(v, (int)dpp_u32<0x108>(id, (uint32_t)v));
   const int m3 = lane_value(v, 48);
   const int m2 = min(lane_value(v, 32), m3);
   const int m1 = min(lane_value(v, 16), m2);
@@ -140,27 +131,24 @@ __device__ __forceinline__ int wave_suffix_min(int v) {
 // added).  Returns the flag "some lane at or before me started a segment".
 // Same DPP steps as wave_scan32 on the (a, b, flag) triple.
 __device__ __forceinline__ bool wave_seg_incl_sum2(uint32_t& a, uint32_t& b, bool start) {
-  const int r = lane_id() & 15;
   uint32_t f = start ? 1u : 0u;
-#define FT_SEG_STEP(CTRL, ROWS, COND)                  \
+  // a lane with no source takes (0, 0, 0), which changes nothing
+#define FT_SEG_STEP(CTRL, ROWS)                        \
   {                                                    \
     const uint32_t ua = dpp_u32<CTRL, ROWS>(0u, a);    \
     const uint32_t ub = dpp_u32<CTRL, ROWS>(0u, b);    \
     const uint32_t uf = dpp_u32<CTRL, ROWS>(0u, f);    \
-    if (COND) {                                        \
-      if (!f) {                                        \
-        a += ua;                                       \
-        b += ub;                                       \
-      }                                                \
-      f |= uf;                                         \
-    }                                                  \
+    const uint32_t keep = f ? 0u : 0xFFFFFFFFu;        \
+    a += ua & keep;                                    \
+    b += ub & keep;                                    \
+    f |= uf;                                           \
   }
-  FT_SEG_STEP(0x111, 0xF, r >= 1)
-  FT_SEG_STEP(0x112, 0xF, r >= 2)
-  FT_SEG_STEP(0x114, 0xF, r >= 4)
-  FT_SEG_STEP(0x118, 0xF, r >= 8)
-  FT_SEG_STEP(0x142, 0xA, true)
-  FT_SEG_STEP(0x143, 0xC, true)
+  FT_SEG_STEP(0x111, 0xF)
+  FT_SEG_STEP(0x112, 0xF)
+  FT_SEG_STEP(0x114, 0xF)
+  FT_SEG_STEP(0x118, 0xF)
+  FT_SEG_STEP(0x142, 0xA)
+  FT_SEG_STEP(0x143, 0xC)
 #undef FT_SEG_STEP
   return f != 0;
 }
