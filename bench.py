@@ -11,7 +11,7 @@ value = Flowtree pairs of the step / step time (the prune included).
 The plain one-launch-per-query Flowtree stage is timed on the same
 candidates afterwards and reported beside it.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload batched|batched_v1m|text|image]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload batched|batched_v1m|text|image|tiny]
        [--no-cpu-baseline] [--no-plain]
        python bench.py --workload act [--act-cand C] [--act-iters I]   (the R-WMD / ACT stage after
                                                               Flowtree: Quadtree 1000 -> Flowtree C -> ACT-I top-20)
@@ -127,6 +127,9 @@ def workload(name):
     if name == "image":
         return gen.make("image"), 0, 10, ("image-shaped: 28x28 grid in R^2, 60000 stroke images and 1000 queries "
                                           "of 100..200 pixels (Q=16); batched Flowtree against all docs, top-10")
+    if name == "tiny":
+        return gen.make("tiny"), 0, 5, ("tiny: V=2000 points in R^16 (20-component Gaussian mixture), 500 docs and "
+                                        "10 queries of 10..30 points; batched Flowtree against all docs, top-5")
     raise SystemExit("unknown workload " + name)
 
 

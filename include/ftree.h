@@ -130,8 +130,9 @@ ft_status ft_quadtree_knn(ft_index* index, const int64_t* q_off, const uint32_t*
  * Arguments as ft_quadtree_knn, plus
  * mode        FT_PLAIN: one kernel launch per query over its candidates;
  *             FT_BATCHED: all (query, candidate) pairs in one persistent
- *             launch per pair-size class, the whole call replayed as one
- *             HIP graph, schedule picked by the built-in autotuner.
+ *             launch per pair-size class, replayed as two HIP graphs
+ *             (bucketing, then the class launches), schedule picked by the
+ *             built-in autotuner.
  * out_cost[n_q*k] float32 Flowtree values 2^-Q * sum eta * ||x - y||_2 in
  *             the units of X, ordered with out_doc by (cost, doc index).
  * The greedy matches, at every cell, the unmatched dataset-side and

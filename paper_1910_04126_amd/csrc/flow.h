@@ -41,7 +41,6 @@ struct FlowLds {
   static constexpr int N = 64 * C * W;
   int64_t work;        // persistent kernels: the grabbed chunk, broadcast
   uint32_t rank[N];    // merged Morton ranks
-  uint32_t res[N];     // unmatched mass
   uint32_t pp[N];      // doc-side inclusive prefix (before the merge: input ranks)
   uint32_t pn[N];      // query-side inclusive prefix (before the merge: input masses)
   uint32_t em_pos[N];  // match: merged position of the doc item | query item << 16
@@ -416,7 +415,7 @@ __device__ __forceinline__ double row_sum_f64(double v) {
 }
 
 // Pairs of matches that share the item of the smaller side (by_doc: the doc
-// item): a counting sort in LDS (res and slot are free once the matching is
+// item): a counting sort in LDS (pp and slot are free once the matching is
 // done) groups the matches by that item, each item's run padded to even
 // length, and unit u is the two entries ord[2u], ord[2u + 1] of L.slot (the
 // second 0xFFFF when the run was odd).  The padded order needs up to
@@ -429,7 +428,7 @@ __device__ int pair_units(FlowLds<C, W>& L, const int E, const int n, const bool
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   using Lds = FlowLds<C, W>;
   static_assert(offsetof(Lds, lcn) == offsetof(Lds, slot) + 2 * Lds::N, "slot and lcn must be adjacent");
-  uint32_t* cnt = L.res;
+  uint32_t* cnt = L.pp;  // the prefix sums are dead, the products not yet written
   uint16_t* ord = L.slot;
   constexpr uint16_t NONE = 0xFFFFu;
   for (int i = tid; i < n; i += 64 * W) cnt[i] = 0u;

@@ -63,9 +63,11 @@ __device__ __forceinline__ void flow_one(FlowLds<C, W>& L, const PairArgs& a, co
 // cost less than the extra wavefront gains (at 128 VGPRs and four wavefronts
 // per SIMD the batched kernels took 4 % longer and the image-grid ones 13 %;
 // the one-wavefront (4,1) class gained 2 % on the batched workload when held
-// to five).
-template <int C, int W>
-constexpr int flow_min_waves() { return C == 4 ? 5 : 1; }
+// to five).  With one lane per match (rows of at most 4 floats) the pricing
+// needs few registers, and six wavefronts at 80 VGPRs ran the image grid 2 %
+// faster (the batched workload, 16 and 8 lanes per match, 30 % slower).
+template <int C, int W, int G>
+constexpr int flow_min_waves() { return C == 4 ? (G == 1 ? 6 : 5) : 1; }
 
 // Plain: workgroup b handles column b of query q.
 template <int C, int W, int G>
@@ -93,7 +95,7 @@ __device__ __forceinline__ void persistent_body(FlowLds<C, W>& L, const PairArgs
 }
 
 template <int C, int W, int G>
-__global__ __launch_bounds__(64 * W, (flow_min_waves<C, W>())) void k_flow_persistent(PairArgs a, const int64_t* __restrict__ list,
+__global__ __launch_bounds__(64 * W, (flow_min_waves<C, W, G>())) void k_flow_persistent(PairArgs a, const int64_t* __restrict__ list,
                                                             const int64_t* __restrict__ offsets, int64_t n_q, int cls,
                                                             uint32_t* __restrict__ counters, int chunk) {
   __shared__ FlowLds<C, W> L;
@@ -115,7 +117,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_num_sgpr(72))) void k_flo
 // n_cols, doc cand[p]): workgroups stride over the list and skip the pairs
 // of other classes (the no-allocation path has no room for class lists).
 template <int C, int W, int G>
-__global__ __launch_bounds__(64 * W, (flow_min_waves<C, W>())) void k_flow_class_stride(PairArgs a, int64_t n_pairs,
+__global__ __launch_bounds__(64 * W, (flow_min_waves<C, W, G>())) void k_flow_class_stride(PairArgs a, int64_t n_pairs,
                                                                                     int cls) {
   __shared__ FlowLds<C, W> L;
   for (int64_t p = blockIdx.x; p < n_pairs; p += gridDim.x) {

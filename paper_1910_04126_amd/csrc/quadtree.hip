@@ -329,8 +329,11 @@ __global__ __launch_bounds__(QP_THREADS) __attribute__((amdgpu_num_sgpr(72))) vo
     __syncthreads();
     // thread t owns docs j * 2048 + 4t + k (j, k < 4): its row reads are
     // 16 bytes at consecutive addresses across the wavefront
+    // (the cell's row, mass and shift are the same for every lane: scalars;
+    // the rows are read at 32-bit byte offsets from the slice's base)
     const int nh = n_hq;
-    const uint32_t* rows = head_rows + (size_t)sl * nhead * QP_HEAD_SLICE + 4 * tid;
+    const char* rbase = reinterpret_cast<const char*>(head_rows + (size_t)sl * nhead * QP_HEAD_SLICE);
+    const uint32_t lane_off = 16u * (uint32_t)tid;
     Acc a16[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) a16[k] = 0;
@@ -340,11 +343,13 @@ __global__ __launch_bounds__(QP_THREADS) __attribute__((amdgpu_num_sgpr(72))) vo
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         const bool live = i + u < nh;
-        const uint32_t* r = rows + (size_t)(live ? hq_id[i + u] : 0) * QP_HEAD_SLICE;
-        am[u] = live ? hq_mass[i + u] : 0u;
-        sh[u] = live ? hq_sh[i + u] : 0u;
+        const uint32_t id = live ? __builtin_amdgcn_readfirstlane((uint32_t)hq_id[i + u]) : 0u;
+        am[u] = live ? __builtin_amdgcn_readfirstlane(hq_mass[i + u]) : 0u;
+        sh[u] = live ? __builtin_amdgcn_readfirstlane((uint32_t)hq_sh[i + u]) : 0u;
+        const uint32_t o = id * (uint32_t)(QP_HEAD_SLICE * 4) + lane_off;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) v[u][j] = live ? *reinterpret_cast<const uint4*>(r + j * 2048) : make_uint4(0, 0, 0, 0);
+        for (int j = 0; j < 4; ++j)
+          v[u][j] = live ? *reinterpret_cast<const uint4*>(rbase + (o + (uint32_t)j * 8192u)) : make_uint4(0, 0, 0, 0);
       }
 #pragma unroll
       for (int u = 0; u < 2; ++u)
