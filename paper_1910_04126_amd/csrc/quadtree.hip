@@ -224,12 +224,13 @@ __global__ __launch_bounds__(1024) void k_post_scan(uint32_t* __restrict__ dir, 
 // touches each cell once, so its lanes never share a counter; the barrier
 // after each doc orders its counter updates before the next doc's.  The
 // directory counters run from each list's start to its end, which is what
-// the ranking kernel reads.
+// the ranking kernel reads.  The doc is stored as the byte offset of its
+// counter in the ranking kernel's LDS array (acc_bytes per counter).
 __global__ __launch_bounds__(64) void k_post_fill(const int64_t* __restrict__ eoff, const uint32_t* __restrict__ ekey,
                                                   const uint32_t* __restrict__ emass, int64_t n_docs, int64_t S,
                                                   int64_t n_cells, const uint32_t* __restrict__ cbase,
                                                   uint32_t* __restrict__ dir, uint16_t* __restrict__ post_doc,
-                                                  uint32_t* __restrict__ post_mass) {
+                                                  uint32_t* __restrict__ post_mass, uint32_t acc_bytes) {
   const int64_t sl = blockIdx.x;
   const int64_t d0 = sl * S, d1 = d0 + S < n_docs ? d0 + S : n_docs;
   uint32_t* D = dir + sl * n_cells;
@@ -239,7 +240,7 @@ __global__ __launch_bounds__(64) void k_post_fill(const int64_t* __restrict__ eo
     const uint32_t local = (uint32_t)(d - d0);
     for (int64_t e = eoff[d] + lane_id(); e < eoff[d + 1]; e += 64) {
       const uint32_t pos = atomicAdd(&D[cell_number(cbase, ekey[e])], 1u);
-      Pd[pos] = (uint16_t)local;
+      Pd[pos] = (uint16_t)(local * acc_bytes);
       Pm[pos] = emass[e];
     }
     __threadfence();
@@ -442,11 +443,13 @@ __global__ __launch_bounds__(QP_THREADS) __attribute__((amdgpu_num_sgpr(72))) vo
       for (int u = 0; u < QP_U; ++u) {
         if (cnt[u] == (uint32_t)QP_PIECE) {
 #pragma unroll
-          for (int j = 0; j < QP_PIECE / 64; ++j) atomicAdd(&acc[ed[u][j]], (Acc)min(am[u], em[u][j]) << sh[u]);
+          for (int j = 0; j < QP_PIECE / 64; ++j)
+            atomicAdd(reinterpret_cast<Acc*>(reinterpret_cast<char*>(acc) + ed[u][j]), (Acc)min(am[u], em[u][j]) << sh[u]);
         } else {
 #pragma unroll
           for (int j = 0; j < QP_PIECE / 64; ++j)
-            if ((uint32_t)(j * 64 + lane) < cnt[u]) atomicAdd(&acc[ed[u][j]], (Acc)min(am[u], em[u][j]) << sh[u]);
+            if ((uint32_t)(j * 64 + lane) < cnt[u])
+              atomicAdd(reinterpret_cast<Acc*>(reinterpret_cast<char*>(acc) + ed[u][j]), (Acc)min(am[u], em[u][j]) << sh[u]);
         }
       }
     }
@@ -631,8 +634,9 @@ static void prepare_postings(ft_index* ix, hipStream_t s) {
   FT_HIP(hipMemcpyAsync(cbase, cb, sizeof(cb), hipMemcpyHostToDevice, s));
   uint32_t* dir = (uint32_t*)ix->post_dir.ensure(n_sl * n_cells * 4);
   FT_HIP(hipMemsetAsync(dir, 0, n_sl * n_cells * 4, s));
-  // list entries as two arrays: doc within the slice (u16, slices hold at
-  // most 8192 docs) and cell mass (u32), 6 bytes an entry
+  // list entries as two arrays: doc within the slice as the byte offset of
+  // its counter (u16: 8192 docs x 4 bytes or 4096 x 8 at most) and cell mass
+  // (u32), 6 bytes an entry
   const int64_t ne = std::max<int64_t>(1, ix->docs.emb_nnz);
   uint16_t* post_doc = (uint16_t*)ix->post.ensure(ne * 6 + 16);
   uint32_t* post_mass = (uint32_t*)((char*)ix->post.p + ((ne * 2 + 15) & ~int64_t(15)));
@@ -641,7 +645,7 @@ static void prepare_postings(ft_index* ix, hipStream_t s) {
   k_post_scan<<<(unsigned)n_sl, 1024, 0, s>>>(dir, n_cells);
   k_post_fill<<<(unsigned)n_sl, 64, 0, s>>>(ix->docs.ecnt.as<int64_t>(), ix->docs.ekey.as<uint32_t>(),
                                             ix->docs.emass.as<uint32_t>(), n, S, n_cells, cbase, dir, post_doc,
-                                            post_mass);
+                                            post_mass, narrow ? 4u : 8u);
   FT_HIP(hipGetLastError());
   FT_HIP(hipStreamSynchronize(s));
   ix->post_slice = S;
