@@ -11,12 +11,14 @@ value = Flowtree pairs of the step / step time (the prune included).
 The plain one-launch-per-query Flowtree stage is timed on the same
 candidates afterwards and reported beside it.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload batched|batched_v1m|text|image|tiny]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload batched|batched_v1m|text|image|tiny|exhaustive]
        [--no-cpu-baseline] [--no-plain]
        python bench.py --workload act [--act-cand C] [--act-iters I]   (the R-WMD / ACT stage after
                                                               Flowtree: Quadtree 1000 -> Flowtree C -> ACT-I top-20)
        python bench.py --workload sinkhorn [--act-cand C] [--sk-iters I]   (Sinkhorn-I in place of ACT)
        python bench.py --workload exact [--act-cand C]   (exact W1 of the best C by Flowtree, C = 20)
+       python bench.py --workload pipeline   (the four stages end to end, queries/s: Quadtree 1000 ->
+                                              Flowtree 100 -> ACT-1 5 -> exact W1 top-1)
        python bench.py --workload random_model [--reps R]   (the Section 3.2 experiment: success
                                                               rate of recovering the planted nearest
                                                               neighbour, Quadtree vs Flowtree, vs N)
@@ -121,6 +123,11 @@ def workload(name):
             "batched with V=1000000 ground points in R^300 (1.2 GB of coordinates, past the 256 MB "
             "Infinity Cache); 1000000 docs and 4096 queries, sizes 5..500 with P(m)~m^-1.1, Zipf(1.1) "
             "words; Quadtree prune to 1000 over all docs, batched Flowtree rerank to top-20")
+    if name == "exhaustive":
+        return gen.make("batched", n_queries=64), 0, 20, (
+            "exhaustive: the batched ground space and 1000000 docs (V=100000 d=300, sizes 5..500 with "
+            "P(m)~m^-1.1, Zipf(1.1) words); 64 queries of the same law, batched Flowtree against every doc "
+            "(64M pairs), top-20")
     if name == "text":
         return gen.make("text"), 1000, 20, ("text-shaped: V=100000 d=300, 100000 docs and 1000 queries of 20..200 "
                                             "words; Quadtree prune to 1000, batched Flowtree rerank to top-20")
@@ -161,6 +168,8 @@ def main():
         return grad_bench(args)
     if args.workload in ("act", "sinkhorn", "exact"):
         return rerank_stage(args, args.workload)
+    if args.workload == "pipeline":
+        return pipeline_bench(args)
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs on a single MI355X "
               "(the multi-GPU sharding is a design note, not built)", file=sys.stderr)
@@ -264,9 +273,11 @@ def main():
     # algorithmic bytes of the Flowtree stage: every candidate doc's items
     # (rank + mass, 8 B) and coordinate rows (4 d B); each query once
     sizes = np.diff(ds.doc_off)
-    cand_h = cand.cpu().numpy() if cand is not None else np.tile(np.arange(ds.n_docs), (n_q, 1))
     row_bytes = 8 + 4 * ds.d
-    doc_bytes = float(sizes[cand_h].sum()) * row_bytes
+    if cand is not None:
+        doc_bytes = float(sizes[cand.cpu().numpy()].sum()) * row_bytes
+    else:
+        doc_bytes = float(n_q) * float(sizes.sum()) * row_bytes
     q_bytes = float(np.diff(ds.q_off).sum()) * row_bytes
     alg_bytes = doc_bytes + q_bytes
     kms = float(np.mean(kernel_ms))
@@ -793,6 +804,114 @@ def rerank_stage(args, method):
     print(json.dumps(out), flush=True)
 
 
+def pipeline_bench(args):
+    """The paper's prefetch-and-prune pipeline (Section 4.3) end to end on
+    the batched workload: Quadtree prunes every doc to 1000, batched
+    Flowtree keeps 100, ACT-1 keeps 5, exact W1 ranks those 5 and keeps the
+    best.  One step is the four calls for all 4096 queries; value = queries
+    per second through all four.  Each stage's time comes from events
+    between the calls."""
+    if args.gpus != 1:
+        print("bench.py measures one GPU only", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_1910_04126_amd as ft
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    C = (1000, 100, 5, 1)
+    t0 = time.time()
+    ds, _, _, desc = workload("batched")
+    log("generated batched workload in %.1fs" % (time.time() - t0))
+
+    def T(a):
+        a = np.ascontiguousarray(a)
+        if a.dtype == np.uint32:
+            a = a.view(np.int32)
+        return torch.from_numpy(a).to(dev)
+
+    ix = ft.build_tree(T(ds.X), ds.shift, ds.B, T(ds.doc_off), T(ds.doc_id), T(ds.doc_mass), ds.Q)
+    if args.no_autotune:
+        ix.set_autotune(0)
+    q = (T(ds.q_off), T(ds.q_id), T(ds.q_mass))
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+
+    def step():
+        ev[0].record()
+        _, fdocs = ft.knn_pipeline(ix, *q, C[0], C[1])
+        ev[1].record()
+        _, adocs = ft.act_knn(ix, *q, C[2], iters=1, cand=fdocs)
+        ev[2].record()
+        w, best = ft.exact_knn(ix, *q, C[3], cand=adocs)
+        ev[3].record()
+        return w, best
+
+    log("warmup x%d" % args.warmup)
+    for _ in range(max(1, args.warmup)):
+        step()
+    torch.cuda.synchronize()
+    st = {"quadtree_flowtree": [], "act": [], "exact": []}
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        w, best = step()
+        torch.cuda.synchronize()
+        st["quadtree_flowtree"].append(ev[0].elapsed_time(ev[1]))
+        st["act"].append(ev[1].elapsed_time(ev[2]))
+        st["exact"].append(ev[2].elapsed_time(ev[3]))
+        log("  step %d: Quadtree+Flowtree %.1f ms, ACT-1 %.1f ms, exact W1 %.1f ms" % (
+            i, st["quadtree_flowtree"][-1], st["act"][-1], st["exact"][-1]))
+    elapsed = time.perf_counter() - t_start
+    ms_step = 1000.0 * elapsed / args.steps
+    n_q = ds.n_queries
+    cpu = None if args.no_cpu_baseline else pipeline_cpu_baseline(ds, C)
+    out = {
+        "metric": "queries/sec through the four-stage pipeline (Quadtree, Flowtree, ACT-1, exact W1) on 1 MI355X",
+        "value": round(n_q / (elapsed / args.steps), 2), "unit": "queries/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": desc + "; then ACT-1 keeps 5 of Flowtree's 100 and exact W1 ranks them to the top-1",
+                   "queries": n_q, "candidates": list(C)},
+        "roofline": None,
+        "stages": {k: round(float(np.mean(v)), 3) for k, v in st.items()},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def pipeline_cpu_baseline(ds, C):
+    """The oracle through the same four stages (Quadtree on every doc, top
+    C[0]; Flowtree, top C[1]; ACT-1 in float64, top C[2]; exact W1 by LP,
+    top C[3]) for whole queries in order, one thread, for about 20 s."""
+    import oracle
+    Tr = oracle.Tree(ds.X, ds.shift, ds.B)
+    docs = np.arange(ds.n_docs)
+    done = 0
+    t_start = time.perf_counter()
+    for qq in range(ds.n_queries):
+        U = Tr.quadtree_pairs(ds.q_off, ds.q_id, ds.q_mass, ds.doc_off, ds.doc_id, ds.doc_mass,
+                              np.full(ds.n_docs, qq), docs, ds.Q)
+        _, c1 = oracle.topk(U, docs, C[0])
+        F = Tr.flowtree_pairs(ds.q_off, ds.q_id, ds.q_mass, ds.doc_off, ds.doc_id, ds.doc_mass,
+                              np.full(len(c1), qq), c1, ds.Q)
+        _, c2 = oracle.topk(F, c1, C[1])
+        A = oracle.act_pairs(ds.X, ds.q_off, ds.q_id, ds.q_mass, ds.doc_off, ds.doc_id, ds.doc_mass,
+                             np.full(len(c2), qq), c2, ds.Q, 1)
+        _, c3 = oracle.topk(A, c2, C[2])
+        qa, qb = ds.q_off[qq], ds.q_off[qq + 1]
+        W = np.array([oracle.exact_w1_lp(ds.X, ds.doc_id[ds.doc_off[d]:ds.doc_off[d + 1]],
+                                         ds.doc_mass[ds.doc_off[d]:ds.doc_off[d + 1]],
+                                         ds.q_id[qa:qb], ds.q_mass[qa:qb], ds.Q) for d in c3])
+        oracle.topk(W, c3, C[3])
+        done += 1
+        if time.perf_counter() - t_start > 20.0:
+            break
+    el = time.perf_counter() - t_start
+    return {"value": round(done / el, 4), "unit": "queries/s", "cores": 1, "kind": "oracle",
+            "sample": "%d of %d queries in order through the four stages (C oracle for Quadtree and "
+                      "Flowtree, float64 numpy ACT-1, LP by HiGHS for exact W1), one thread" % (done, ds.n_queries)}
+
+
 def rerank_cpu_baseline(ds, fdocs, method, iters):
     """The float64 oracle (ACT, Sinkhorn or exact W1) on a bounded sample of the same
     pairs (queries in order, all their candidates), single-threaded."""
@@ -845,47 +964,63 @@ def cpu_threads():
     return max(1, n)
 
 
+# With no prune over this many docs, one query of the CPU oracle takes far
+# longer than the sample's budget: the sample is then cut into (query, block
+# of docs) items, each ranked on its own.
+ORACLE_DOC_BLOCK = 2000
+ORACLE_BLOCKED_DOCS = 100_000
+
+
 def _oracle_pipeline(ds, prune, k, n_cols, threads, budget):
     """Whole-pipeline queries of the CPU oracle (Quadtree on every doc,
     top-`prune`, Flowtree on those, top-k; or Flowtree on every doc when
     prune = 0), one query per thread at a time, each thread with its own
-    oracle tree, until `budget` seconds have passed.  Returns (queries done,
-    seconds)."""
+    oracle tree, until `budget` seconds have passed.  Without a prune over
+    more than ORACLE_BLOCKED_DOCS docs an item is one query against a block
+    of ORACLE_DOC_BLOCK docs (Flowtree, top-k of the block).  Returns
+    (Flowtree pairs done, seconds, items done)."""
     import itertools
     import threading
 
     import oracle
     trees = [oracle.Tree(ds.X, ds.shift, ds.B) for _ in range(threads)]
     docs = np.arange(ds.n_docs)
-    next_q = itertools.count()
+    blocked = not prune and ds.n_docs > ORACLE_BLOCKED_DOCS
+    n_blocks = -(-ds.n_docs // ORACLE_DOC_BLOCK) if blocked else 1
+    next_item = itertools.count()
     lock = threading.Lock()
     done = [0] * threads
+    pairs = [0] * threads
     t_start = time.perf_counter()
 
     def worker(i):
         Tr = trees[i]
         while time.perf_counter() - t_start < budget:
             with lock:
-                q = next(next_q)
+                item = next(next_item)
+            q, b = divmod(item, n_blocks)
             if q >= ds.n_queries:
                 return
             if prune:
                 U = Tr.quadtree_pairs(ds.q_off, ds.q_id, ds.q_mass, ds.doc_off, ds.doc_id, ds.doc_mass,
                                       np.full(ds.n_docs, q), docs, ds.Q)
                 _, cand = oracle.topk(U, docs, prune)
+            elif blocked:
+                cand = docs[b * ORACLE_DOC_BLOCK:(b + 1) * ORACLE_DOC_BLOCK]
             else:
                 cand = docs
             F = Tr.flowtree_pairs(ds.q_off, ds.q_id, ds.q_mass, ds.doc_off, ds.doc_id, ds.doc_mass,
                                   np.full(len(cand), q), cand, ds.Q)
-            oracle.topk(F, cand, k)
+            oracle.topk(F, cand, min(k, len(cand)))
             done[i] += 1
+            pairs[i] += len(cand)
 
     ths = [threading.Thread(target=worker, args=(i,)) for i in range(threads)]
     for th in ths:
         th.start()
     for th in ths:
         th.join()
-    return sum(done), time.perf_counter() - t_start
+    return sum(pairs), time.perf_counter() - t_start, sum(done)
 
 
 def cpu_baseline(ds, prune, k, n_cols):
@@ -895,19 +1030,22 @@ def cpu_baseline(ds, prune, k, n_cols):
     times its implementation) and once on all host cores with one query per
     thread; scaled to Flowtree pairs per second of that pipeline.  The main
     value is the all-cores leg."""
+    blocked = not prune and ds.n_docs > ORACLE_BLOCKED_DOCS
     what = (("Quadtree on all %d docs, top-%d, Flowtree, top-%d" % (ds.n_docs, prune, k)) if prune else
-            ("Flowtree on all %d docs, top-%d" % (ds.n_docs, k)))
-    n1, t1 = _oracle_pipeline(ds, prune, k, n_cols, 1, 15.0)
-    log("cpu baseline: 1 thread, %d queries in %.1fs" % (n1, t1))
+            ("Flowtree on blocks of %d of the %d docs, top-%d of each block" % (ORACLE_DOC_BLOCK, ds.n_docs, k))
+            if blocked else ("Flowtree on all %d docs, top-%d" % (ds.n_docs, k)))
+    unit = "(query, doc block) items" if blocked else "queries"
+    p1, t1, n1 = _oracle_pipeline(ds, prune, k, n_cols, 1, 15.0)
+    log("cpu baseline: 1 thread, %d %s in %.1fs" % (n1, unit, t1))
     nt = cpu_threads()
-    nn, tn = _oracle_pipeline(ds, prune, k, n_cols, nt, 15.0)
-    log("cpu baseline: %d threads, %d queries in %.1fs" % (nt, nn, tn))
-    return {"value": round(nn * n_cols / tn, 2), "unit": "pairs/s", "cores": nt, "kind": "oracle",
-            "sample": "%d of %d queries through the whole pipeline (%s), C oracle on %d host threads, one "
-                      "query per thread; pairs/s counts the Flowtree pairs of those queries" %
-                      (nn, ds.n_queries, what, nt),
-            "single_thread": {"value": round(n1 * n_cols / t1, 2), "unit": "pairs/s", "cores": 1,
-                              "sample": "%d queries, same pipeline, one thread" % n1}}
+    pn, tn, nn = _oracle_pipeline(ds, prune, k, n_cols, nt, 15.0)
+    log("cpu baseline: %d threads, %d %s in %.1fs" % (nt, nn, unit, tn))
+    return {"value": round(pn / tn, 2), "unit": "pairs/s", "cores": nt, "kind": "oracle",
+            "sample": "%d %s of the %d queries through the whole pipeline (%s), C oracle on %d host threads, "
+                      "one item per thread; pairs/s counts the Flowtree pairs of those items" %
+                      (nn, unit, ds.n_queries, what, nt),
+            "single_thread": {"value": round(p1 / t1, 2), "unit": "pairs/s", "cores": 1,
+                              "sample": "%d %s, same pipeline, one thread" % (n1, unit)}}
 
 
 if __name__ == "__main__":
