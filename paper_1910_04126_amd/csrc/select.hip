@@ -297,14 +297,21 @@ __global__ __launch_bounds__(1024) void k_topk_window(const K* __restrict__ keys
   for (int64_t c = threadIdx.x; c < n; c += blockDim.x) {
     const uint64_t x = sort_bits(rk[c]);
     const uint64_t h = shr64(x, hs);
+    // (below < k <= 1024 keys lie under the bucket and nties <= TIE_CAP in
+    // it when every key lies in [min, max]; the bounds keep the writes in
+    // their arrays even for a row that breaks that)
     if (h < sel) {
       const uint32_t p = atomicAdd(&s_nl, 1u);
-      sk[p] = x;
-      sd[p] = (uint32_t)c;
+      if (p < 1024u) {
+        sk[p] = x;
+        sd[p] = (uint32_t)c;
+      }
     } else if (h == sel && !many) {
       const uint32_t p = atomicAdd(&s_nt, 1u);
-      tk[p] = x;
-      td[p] = (uint32_t)c;
+      if (p < (uint32_t)TIE_CAP) {
+        tk[p] = x;
+        td[p] = (uint32_t)c;
+      }
     }
   }
   if (many) {
