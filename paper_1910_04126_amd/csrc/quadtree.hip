@@ -402,29 +402,38 @@ __global__ __launch_bounds__(QP_THREADS) __attribute__((amdgpu_num_sgpr(72))) vo
     // its last) needs no per-lane bound
     const char* pd_base = reinterpret_cast<const char*>(Pd);
     const char* pm_base = reinterpret_cast<const char*>(Pm);
+    // piece p's entry count, query mass, shift and first entry (zero count
+    // past the last piece)
+    auto piece = [&](uint32_t p, uint32_t& c, uint32_t& a, uint32_t& s, uint32_t& at) {
+      c = a = s = at = 0;
+      if (p < n_pieces) {
+        const uint32_t it = pitem[p];
+        const uint4 item = items[it];
+        const uint32_t off = (p - pstart[it]) * QP_PIECE;
+        c = min((uint32_t)QP_PIECE, item.y - off);
+        a = item.z;
+        s = item.w;
+        at = item.x + off;
+      }
+      c = __builtin_amdgcn_readfirstlane(c);
+      a = __builtin_amdgcn_readfirstlane(a);
+      s = __builtin_amdgcn_readfirstlane(s);
+      at = __builtin_amdgcn_readfirstlane(at);
+    };
+    // The next pieces' descriptors are read from LDS after this round's list
+    // loads are issued and before its atomics: LDS operations complete in
+    // order, so waiting for them does not wait for the atomics, and the next
+    // loads go out while the atomics drain.
+    uint32_t cnt[QP_U], am[QP_U], sh[QP_U], at[QP_U];
+#pragma unroll
+    for (int u = 0; u < QP_U; ++u) piece(w * QP_U + u, cnt[u], am[u], sh[u], at[u]);
     for (uint32_t p0 = w * QP_U; p0 < n_pieces; p0 += QP_WAVES * QP_U) {
       uint32_t ed[QP_U][QP_PIECE / 64], em[QP_U][QP_PIECE / 64];
-      uint32_t am[QP_U], sh[QP_U], cnt[QP_U];
 #pragma unroll
       for (int u = 0; u < QP_U; ++u) {
-        const uint32_t p = p0 + u;
-        uint32_t c = 0, a = 0, s = 0, at = 0;
-        if (p < n_pieces) {
-          const uint32_t it = pitem[p];
-          const uint4 item = items[it];
-          const uint32_t off = (p - pstart[it]) * QP_PIECE;
-          c = min((uint32_t)QP_PIECE, item.y - off);
-          a = item.z;
-          s = item.w;
-          at = item.x + off;
-        }
-        cnt[u] = __builtin_amdgcn_readfirstlane(c);
-        am[u] = __builtin_amdgcn_readfirstlane(a);
-        sh[u] = __builtin_amdgcn_readfirstlane(s);
-        at = __builtin_amdgcn_readfirstlane(at);
         if (cnt[u] == (uint32_t)QP_PIECE) {
-          const char* pd_lane = pd_base + 2u * (at + lane);
-          const char* pm_lane = pm_base + 4u * (at + lane);
+          const char* pd_lane = pd_base + 2u * (at[u] + lane);
+          const char* pm_lane = pm_base + 4u * (at[u] + lane);
 #pragma unroll
           for (int j = 0; j < QP_PIECE / 64; ++j) {
             ed[u][j] = *reinterpret_cast<const uint16_t*>(pd_lane + 128 * j);
@@ -434,11 +443,14 @@ __global__ __launch_bounds__(QP_THREADS) __attribute__((amdgpu_num_sgpr(72))) vo
 #pragma unroll
           for (int j = 0; j < QP_PIECE / 64; ++j) {
             const uint32_t x = j * 64 + lane;
-            ed[u][j] = x < cnt[u] ? (uint32_t)*reinterpret_cast<const uint16_t*>(pd_base + 2u * (at + x)) : 0u;
-            em[u][j] = x < cnt[u] ? *reinterpret_cast<const uint32_t*>(pm_base + 4u * (at + x)) : 0u;
+            ed[u][j] = x < cnt[u] ? (uint32_t)*reinterpret_cast<const uint16_t*>(pd_base + 2u * (at[u] + x)) : 0u;
+            em[u][j] = x < cnt[u] ? *reinterpret_cast<const uint32_t*>(pm_base + 4u * (at[u] + x)) : 0u;
           }
         }
       }
+      uint32_t ncnt[QP_U], nam[QP_U], nsh[QP_U], nat[QP_U];
+#pragma unroll
+      for (int u = 0; u < QP_U; ++u) piece(p0 + QP_WAVES * QP_U + u, ncnt[u], nam[u], nsh[u], nat[u]);
 #pragma unroll
       for (int u = 0; u < QP_U; ++u) {
         if (cnt[u] == (uint32_t)QP_PIECE) {
@@ -451,6 +463,13 @@ __global__ __launch_bounds__(QP_THREADS) __attribute__((amdgpu_num_sgpr(72))) vo
             if ((uint32_t)(j * 64 + lane) < cnt[u])
               atomicAdd(reinterpret_cast<Acc*>(reinterpret_cast<char*>(acc) + ed[u][j]), (Acc)min(am[u], em[u][j]) << sh[u]);
         }
+      }
+#pragma unroll
+      for (int u = 0; u < QP_U; ++u) {
+        cnt[u] = ncnt[u];
+        am[u] = nam[u];
+        sh[u] = nsh[u];
+        at[u] = nat[u];
       }
     }
     __syncthreads();
