@@ -57,7 +57,60 @@ struct ExactArgs {
   int64_t slot;
   uint32_t* status;
   float* cost;            // knn form: [query * n_cols + column]; pairs form: [pair]
+  const int64_t* order;   // pairs in the order they are taken: largest estimated work first
+  unsigned long long* next;  // work counter, zero at launch
 };
+
+// The (query, doc) of pair p, in either form.
+__device__ __forceinline__ void exact_pair(const ExactArgs& a, int64_t p, int64_t& q, int64_t& doc) {
+  if (a.pair_q) {
+    q = a.pair_q[p];
+    doc = a.pair_d[p];
+  } else {
+    q = p / a.n_cols;
+    const int64_t c = p - q * a.n_cols;
+    doc = a.cand ? a.cand[p] : c;
+  }
+}
+
+// Largest-first order of the pairs, by a bucket of their estimated work
+// s_q * s_d * (s_q + s_d) (a round per item at most, each over the s_q * s_d
+// edges): 64 buckets by the estimate's highest bit, taken from the highest.
+constexpr int EX_BUCKETS = 64;
+
+__global__ void k_exact_zero(unsigned long long* __restrict__ p, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0ull;
+}
+
+__global__ void k_exact_bucket(ExactArgs a, unsigned long long* __restrict__ cnt, uint8_t* __restrict__ bkt) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= a.n_pairs) return;
+  int64_t q, doc;
+  exact_pair(a, p, q, doc);
+  const uint64_t nq = (uint64_t)(a.q_off[q + 1] - a.q_off[q]), nd = (uint64_t)(a.d_off[doc + 1] - a.d_off[doc]);
+  const uint64_t est = nq * nd * (nq + nd) | 1ull;
+  const int b = 63 - __clzll((long long)est);
+  bkt[p] = (uint8_t)b;
+  atomicAdd(&cnt[b], 1ull);
+}
+
+// One thread: bucket starts, highest bucket first (cnt becomes the cursor).
+__global__ void k_exact_scan(unsigned long long* __restrict__ cnt) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  unsigned long long at = 0;
+  for (int b = EX_BUCKETS - 1; b >= 0; --b) {
+    const unsigned long long c = cnt[b];
+    cnt[b] = at;
+    at += c;
+  }
+}
+
+__global__ void k_exact_scatter(int64_t n_pairs, const uint8_t* __restrict__ bkt, unsigned long long* __restrict__ cur,
+                                int64_t* __restrict__ order) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_pairs) return;
+  order[atomicAdd(&cur[bkt[p]], 1ull)] = p;
+}
 
 constexpr uint16_t EX_NONE = 0xFFFF;
 
@@ -88,16 +141,17 @@ __global__ __launch_bounds__(64) void k_exact(ExactArgs a) {
   const int lane = threadIdx.x;
   float* S = a.scratch + (int64_t)blockIdx.x * 2 * a.slot;
   uint32_t* F = (uint32_t*)(S + a.slot);
-  for (int64_t p = blockIdx.x; p < a.n_pairs; p += gridDim.x) {
+  // pairs are taken from a counter in the largest-first order, so the
+  // longest solves start first and the last ones to finish are short
+  for (;;) {
+    unsigned long long t = 0ull;
+    if (lane == 0) t = atomicAdd(a.next, 1ull);
+    const int64_t i = (int64_t)(((unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(t >> 32)) << 32) |
+                                (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)t));
+    if (i >= a.n_pairs) break;
+    const int64_t p = a.order[i];
     int64_t q, doc;
-    if (a.pair_q) {
-      q = a.pair_q[p];
-      doc = a.pair_d[p];
-    } else {
-      q = p / a.n_cols;
-      const int64_t c = p - q * a.n_cols;
-      doc = a.cand ? a.cand[p] : c;
-    }
+    exact_pair(a, p, q, doc);
     const int64_t qa = a.q_off[q], da = a.d_off[doc];
     const int nq = __builtin_amdgcn_readfirstlane((int)(a.q_off[q + 1] - qa));
     const int nd = __builtin_amdgcn_readfirstlane((int)(a.d_off[doc + 1] - da));
@@ -321,6 +375,19 @@ static void launch_exact(ft_index* ix, ExactArgs a, hipStream_t s) {
   int64_t grid = std::min<int64_t>((int64_t)ix->n_cu * std::max(1, per_cu), a.n_pairs);
   grid = std::max<int64_t>(1, std::min<int64_t>(grid, budget / (2 * a.slot)));
   a.scratch = (float*)ix->ws_rerank.ensure((size_t)(grid * 2 * a.slot) * sizeof(float));
+  // work counter and bucket cursors, then the bucket of each pair and the order
+  const int64_t n = a.n_pairs;
+  char* w = (char*)ix->ws_misc.ensure(8 * (1 + EX_BUCKETS) + ((n + 15) & ~int64_t(15)) + 8 * n);
+  unsigned long long* next = (unsigned long long*)w;
+  unsigned long long* cnt = next + 1;
+  uint8_t* bkt = (uint8_t*)(cnt + EX_BUCKETS);
+  int64_t* order = (int64_t*)(bkt + ((n + 15) & ~int64_t(15)));
+  k_exact_zero<<<1, 64, 0, s>>>(next, 1 + EX_BUCKETS);
+  k_exact_bucket<<<(unsigned)ceil_div(n, 256), 256, 0, s>>>(a, cnt, bkt);
+  k_exact_scan<<<1, 1, 0, s>>>(cnt);
+  k_exact_scatter<<<(unsigned)ceil_div(n, 256), 256, 0, s>>>(n, bkt, cnt, order);
+  a.order = order;
+  a.next = next;
   k_exact<<<dim3((unsigned)grid), 64, 0, s>>>(a);
   FT_HIP(hipGetLastError());
 }
