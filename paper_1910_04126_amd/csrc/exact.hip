@@ -114,13 +114,17 @@ __global__ void k_exact_scatter(int64_t n_pairs, const uint8_t* __restrict__ bkt
 
 constexpr uint16_t EX_NONE = 0xFFFF;
 
+// Per-item arrays for supports of at most NMAX items: 28 KB at 512 (five
+// workgroups per CU), 51 KB at FT_MAX_SUPPORT = 1024 (three).
+template <int NMAX>
 struct ExactLds {
+  static_assert(2 * NMAX * sizeof(uint16_t) <= sizeof(BlockLds::tile), "level lists live in the block tile");
   BlockLds blk;
-  double ps[FT_MAX_SUPPORT], pt[FT_MAX_SUPPORT];  // potentials: doc items, query items
-  double ds[FT_MAX_SUPPORT], dt[FT_MAX_SUPPORT];  // Dijkstra distances (reduced costs)
-  uint32_t es[FT_MAX_SUPPORT], et[FT_MAX_SUPPORT];  // supply / demand not yet moved
-  uint16_t prs[FT_MAX_SUPPORT], prt[FT_MAX_SUPPORT];  // predecessor on the other side
-  uint8_t vs[FT_MAX_SUPPORT], vt[FT_MAX_SUPPORT];  // settled
+  double ps[NMAX], pt[NMAX];  // potentials: doc items, query items
+  double ds[NMAX], dt[NMAX];  // Dijkstra distances (reduced costs)
+  uint32_t es[NMAX], et[NMAX];  // supply / demand not yet moved
+  uint16_t prs[NMAX], prt[NMAX];  // predecessor on the other side
+  uint8_t vs[NMAX], vt[NMAX];  // settled
   uint32_t delta;  // the round's push, for every lane
 };
 
@@ -136,8 +140,9 @@ __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
   return v;
 }
 
+template <int NMAX>
 __global__ __launch_bounds__(64) void k_exact(ExactArgs a) {
-  __shared__ ExactLds L;
+  __shared__ ExactLds<NMAX> L;
   const int lane = threadIdx.x;
   float* S = a.scratch + (int64_t)blockIdx.x * 2 * a.slot;
   uint32_t* F = (uint32_t*)(S + a.slot);
@@ -155,7 +160,7 @@ __global__ __launch_bounds__(64) void k_exact(ExactArgs a) {
     const int64_t qa = a.q_off[q], da = a.d_off[doc];
     const int nq = __builtin_amdgcn_readfirstlane((int)(a.q_off[q + 1] - qa));
     const int nd = __builtin_amdgcn_readfirstlane((int)(a.d_off[doc + 1] - da));
-    if ((int64_t)nq * nd > a.slot) {  // the host sizes the slots; never taken
+    if ((int64_t)nq * nd > a.slot || nq > NMAX || nd > NMAX) {  // the host sizes both; never taken
       if (lane == 0) atomicOr(a.status, ERR_SIZE);
       continue;
     }
@@ -210,7 +215,7 @@ __global__ __launch_bounds__(64) void k_exact(ExactArgs a) {
       // the nodes settled at one distance level (ids), in the block tile,
       // free after the distance pass
       uint16_t* bs = reinterpret_cast<uint16_t*>(&L.blk.tile[0][0]);
-      uint16_t* bt = bs + FT_MAX_SUPPORT;
+      uint16_t* bt = bs + NMAX;
       while (true) {
         // the level: the smallest distance of a node not yet settled
         double bd = INFINITY;
@@ -365,13 +370,17 @@ static ExactArgs exact_args(ft_index* ix) {
 }
 
 // Persistent grid: as many workgroups as are resident at once, fewer when
-// the slots (distances and flows) would pass 4 GiB.
+// the slots (distances and flows) would pass 4 GiB.  Supports of at most 512
+// items take the 512-item LDS layout.
 static void launch_exact(ft_index* ix, ExactArgs a, hipStream_t s) {
   if (a.n_pairs <= 0) return;
   a.slot = std::max<int64_t>(1, (int64_t)ix->docs.max_size * ix->qry.max_size);
   const int64_t budget = int64_t(1) << 30;  // words
+  // the smaller LDS layout when every support fits it
+  const bool small = std::max(ix->docs.max_size, ix->qry.max_size) <= 512;
+  const void* kern = small ? (const void*)k_exact<512> : (const void*)k_exact<FT_MAX_SUPPORT>;
   int per_cu = 0;
-  FT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_exact, 64, 0));
+  FT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64, 0));
   int64_t grid = std::min<int64_t>((int64_t)ix->n_cu * std::max(1, per_cu), a.n_pairs);
   grid = std::max<int64_t>(1, std::min<int64_t>(grid, budget / (2 * a.slot)));
   a.scratch = (float*)ix->ws_rerank.ensure((size_t)(grid * 2 * a.slot) * sizeof(float));
@@ -388,7 +397,10 @@ static void launch_exact(ft_index* ix, ExactArgs a, hipStream_t s) {
   k_exact_scatter<<<(unsigned)ceil_div(n, 256), 256, 0, s>>>(n, bkt, cnt, order);
   a.order = order;
   a.next = next;
-  k_exact<<<dim3((unsigned)grid), 64, 0, s>>>(a);
+  if (small)
+    k_exact<512><<<dim3((unsigned)grid), 64, 0, s>>>(a);
+  else
+    k_exact<FT_MAX_SUPPORT><<<dim3((unsigned)grid), 64, 0, s>>>(a);
   FT_HIP(hipGetLastError());
 }
 

@@ -92,6 +92,25 @@ def test_exact_pairs_sizes(ft):
     check_values(got, oracle_w1(ds, qo, qi, qm, pq, pd, "lp"), "exact W1")
 
 
+def test_exact_pairs_large_support(ft):
+    """Queries of 513 and 1024 points (past the 512-item LDS layout, so the
+    1024-item one runs) against docs of up to 80 points, and a 512-point
+    query on its own index (the 512-item layout at its edge); successive
+    shortest paths oracle."""
+    say("exact W1 pairs: queries of 512, 513 and 1024 points in R^300, docs up to 80 points")
+    ds = gen.make("text", V=4000, n_docs=60, n_queries=1, lo=1, hi=80)
+    rng = np.random.default_rng(23)
+    sizes = np.diff(ds.doc_off)
+    docs = np.concatenate([np.argsort(sizes)[-2:], rng.choice(ds.n_docs, 2, replace=False)])
+    for qsizes in ([512], [513, 1024]):
+        qo, qi, qm = csr(rng, qsizes, ds.V, ds.Q)
+        ix = build_index(ft, ds)
+        pq = np.repeat(np.arange(len(qsizes)), len(docs))
+        pd = np.tile(docs, len(qsizes))
+        got = ft.exact_pairs(ix, t(qo), t(qi), t(qm), t(pq), t(pd)).cpu().numpy()
+        check_values(got, oracle_w1(ds, qo, qi, qm, pq, pd, "ssp"), "exact W1, queries of %s points" % qsizes)
+
+
 def test_exact_pairs_grid_ties(ft):
     say("exact W1 pairs: 28x28 grid, stroke images of 20..60 pixels (many equal costs)")
     ds = gen.make("image", n_docs=100, n_queries=4, lo=20, hi=60)
