@@ -228,20 +228,23 @@ __global__ __launch_bounds__(64) void k_exact(ExactArgs a) {
           failed = true;
           break;
         }
-        // a query item with unmet demand at this level ends the search
+        // one pass over the query items: a query item with unmet demand at
+        // this level ends the search (the lowest index); else count the
+        // level's nodes on both sides, then settle them
         uint32_t tj = 0xFFFFFFFFu;
+        int cs = 0, ct = 0;
         for (int j = lane; j < nq; j += 64)
-          if (!L.vt[j] && L.dt[j] == bd && L.et[j] > 0 && (uint32_t)j < tj) tj = (uint32_t)j;
+          if (!L.vt[j] && L.dt[j] == bd) {
+            ++ct;
+            if (L.et[j] > 0 && (uint32_t)j < tj) tj = (uint32_t)j;
+          }
         tj = wave_min_u32(tj);
         if (tj != 0xFFFFFFFFu) {
           target = (int)tj;
           dist_t = bd;
           break;
         }
-        // settle every node of the level, then relax from all of them
-        int cs = 0, ct = 0;
         for (int i = lane; i < nd; i += 64) cs += (!L.vs[i] && L.ds[i] == bd) ? 1 : 0;
-        for (int j = lane; j < nq; j += 64) ct += (!L.vt[j] && L.dt[j] == bd) ? 1 : 0;
         const int os = wave_incl_sum(cs) - cs, ot = wave_incl_sum(ct) - ct;
         const int ns = __shfl(os + cs, 63, 64), nt = __shfl(ot + ct, 63, 64);
         {
@@ -265,6 +268,7 @@ __global__ __launch_bounds__(64) void k_exact(ExactArgs a) {
           double best = L.dt[j];
           int pred = L.prt[j];
           const double pj = L.pt[j];
+#pragma unroll 4
           for (int b = 0; b < ns; ++b) {
             const int i = bs[b];
             const double rc = (double)S[(int64_t)i * nq + j] + L.ps[i] - pj;
