@@ -198,11 +198,14 @@ __global__ __launch_bounds__(64) void k_exact(ExactArgs a) {
         failed = true;
         break;
       }
-      // Dijkstra from every doc item with supply left
+      // Dijkstra from every doc item with supply left; lmin is this lane's
+      // smallest distance among its unsettled nodes
+      double lmin = INFINITY;
       for (int i = lane; i < nd; i += 64) {
         L.ds[i] = L.es[i] > 0 ? 0.0 : INFINITY;
         L.prs[i] = EX_NONE;
         L.vs[i] = 0;
+        lmin = fmin(lmin, L.ds[i]);
       }
       for (int j = lane; j < nq; j += 64) {
         L.dt[j] = INFINITY;
@@ -212,56 +215,52 @@ __global__ __launch_bounds__(64) void k_exact(ExactArgs a) {
       __syncthreads();
       int target = -1;
       double dist_t = 0.0;
-      // the nodes settled at one distance level (ids), in the block tile,
-      // free after the distance pass
+      // the nodes settled at one distance level (ids, in index order), in
+      // the block tile, free after the distance pass
       uint16_t* bs = reinterpret_cast<uint16_t*>(&L.blk.tile[0][0]);
       uint16_t* bt = bs + NMAX;
+      const unsigned long long below = (1ull << lane) - 1ull;
       while (true) {
         // the level: the smallest distance of a node not yet settled
-        double bd = INFINITY;
-        for (int j = lane; j < nq; j += 64)
-          if (!L.vt[j] && L.dt[j] < bd) bd = L.dt[j];
-        for (int i = lane; i < nd; i += 64)
-          if (!L.vs[i] && L.ds[i] < bd) bd = L.ds[i];
-        bd = wave_min_f64(bd);
+        const double bd = wave_min_f64(lmin);
         if (bd == INFINITY) {  // no path to unmet demand: cannot happen for valid masses
           failed = true;
           break;
         }
-        // one pass over the query items: a query item with unmet demand at
-        // this level ends the search (the lowest index); else count the
-        // level's nodes on both sides, then settle them
+        // the level's query items, in index order; one with unmet demand
+        // ends the search (the lowest index)
         uint32_t tj = 0xFFFFFFFFu;
-        int cs = 0, ct = 0;
-        for (int j = lane; j < nq; j += 64)
-          if (!L.vt[j] && L.dt[j] == bd) {
-            ++ct;
-            if (L.et[j] > 0 && (uint32_t)j < tj) tj = (uint32_t)j;
-          }
+        int nt = 0;
+        for (int j0 = 0; j0 < nq; j0 += 64) {
+          const int j = j0 + lane;
+          const bool eq = j < nq && !L.vt[j] && L.dt[j] == bd;
+          if (eq && L.et[j] > 0 && (uint32_t)j < tj) tj = (uint32_t)j;
+          const unsigned long long m = __ballot(eq);
+          if (eq) bt[nt + __popcll(m & below)] = (uint16_t)j;
+          nt += __popcll(m);
+        }
         tj = wave_min_u32(tj);
         if (tj != 0xFFFFFFFFu) {
           target = (int)tj;
           dist_t = bd;
           break;
         }
-        for (int i = lane; i < nd; i += 64) cs += (!L.vs[i] && L.ds[i] == bd) ? 1 : 0;
-        const int os = wave_incl_sum(cs) - cs, ot = wave_incl_sum(ct) - ct;
-        const int ns = __shfl(os + cs, 63, 64), nt = __shfl(ot + ct, 63, 64);
-        {
-          int w = os;
-          for (int i = lane; i < nd; i += 64)
-            if (!L.vs[i] && L.ds[i] == bd) {
-              bs[w++] = (uint16_t)i;
-              L.vs[i] = 1;
-            }
-          w = ot;
-          for (int j = lane; j < nq; j += 64)
-            if (!L.vt[j] && L.dt[j] == bd) {
-              bt[w++] = (uint16_t)j;
-              L.vt[j] = 1;
-            }
+        // the level's doc items, in index order; then settle both sides
+        int ns = 0;
+        for (int i0 = 0; i0 < nd; i0 += 64) {
+          const int i = i0 + lane;
+          const bool eq = i < nd && !L.vs[i] && L.ds[i] == bd;
+          const unsigned long long m = __ballot(eq);
+          if (eq) {
+            bs[ns + __popcll(m & below)] = (uint16_t)i;
+            L.vs[i] = 1;
+          }
+          ns += __popcll(m);
         }
         __syncthreads();
+        for (int b = lane; b < nt; b += 64) L.vt[bt[b]] = 1;
+        __syncthreads();
+        lmin = INFINITY;
         // forward edges from the level's doc items
         for (int j = lane; j < nq; j += 64) {
           if (L.vt[j]) continue;
@@ -280,6 +279,7 @@ __global__ __launch_bounds__(64) void k_exact(ExactArgs a) {
           }
           L.dt[j] = best;
           L.prt[j] = (uint16_t)pred;
+          lmin = fmin(lmin, best);
         }
         // backward edges from the level's query items, where a flow is positive
         for (int i = lane; i < nd; i += 64) {
@@ -300,6 +300,7 @@ __global__ __launch_bounds__(64) void k_exact(ExactArgs a) {
           }
           L.ds[i] = best;
           L.prs[i] = (uint16_t)pred;
+          lmin = fmin(lmin, best);
         }
         __syncthreads();
       }
