@@ -128,16 +128,39 @@ struct ExactLds {
   uint32_t delta;  // the round's push, for every lane
 };
 
+// Wavefront minima on DPP moves (row shifts of 1, 2, 4, 8, then lane 15 of
+// each row to the next and lane 31 to rows 2 and 3): lane 63 ends with the
+// minimum, read back as a scalar.  A lane with no source takes the identity.
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ double dpp_min_f64(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint64_t id = __builtin_bit_cast(uint64_t, (double)INFINITY);
+  const uint32_t lo = dpp_u32<CTRL, ROWS>((uint32_t)id, (uint32_t)b);
+  const uint32_t hi = dpp_u32<CTRL, ROWS>((uint32_t)(id >> 32), (uint32_t)(b >> 32));
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 __device__ __forceinline__ double wave_min_f64(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-  return v;
+  v = fmin(v, dpp_min_f64<0x111>(v));
+  v = fmin(v, dpp_min_f64<0x112>(v));
+  v = fmin(v, dpp_min_f64<0x114>(v));
+  v = fmin(v, dpp_min_f64<0x118>(v));
+  v = fmin(v, dpp_min_f64<0x142, 0xA>(v));
+  v = fmin(v, dpp_min_f64<0x143, 0xC>(v));
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, 63);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), 63);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
 __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o, 64));
-  return v;
+  v = min(v, dpp_u32<0x111>(0xFFFFFFFFu, v));
+  v = min(v, dpp_u32<0x112>(0xFFFFFFFFu, v));
+  v = min(v, dpp_u32<0x114>(0xFFFFFFFFu, v));
+  v = min(v, dpp_u32<0x118>(0xFFFFFFFFu, v));
+  v = min(v, dpp_u32<0x142, 0xA>(0xFFFFFFFFu, v));
+  v = min(v, dpp_u32<0x143, 0xC>(0xFFFFFFFFu, v));
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
 template <int NMAX>
