@@ -269,6 +269,40 @@ __global__ __launch_bounds__(64) void k_head_fill(const int64_t* __restrict__ eo
   }
 }
 
+// Workgroup per query, once per call: the query's cells split into its head
+// cells (head row, mass, shift; at most QP_HEAD_MAX) and the others (cell
+// number, mass, shift), so that the ranking kernel's workgroups, one per
+// (query, slice), read them ready instead of looking each cell up again.
+// The order within each list is arbitrary (the sums are exact integers).
+__global__ __launch_bounds__(256) void k_qt_prep(const int64_t* __restrict__ q_eoff, const uint32_t* __restrict__ q_ekey,
+                                                 const uint32_t* __restrict__ q_emass,
+                                                 const uint32_t* __restrict__ cbase,
+                                                 const uint8_t* __restrict__ hcell, int top, int64_t q0,
+                                                 uint2* __restrict__ counts, uint2* __restrict__ head,
+                                                 uint4* __restrict__ listed) {
+  __shared__ uint32_t nh, nl;
+  const int64_t q = q0 + blockIdx.x;
+  if (threadIdx.x == 0) nh = nl = 0u;
+  __syncthreads();
+  const int64_t e0 = q_eoff[q], ne = q_eoff[q + 1] - e0;
+  for (int64_t e = threadIdx.x; e < ne; e += blockDim.x) {
+    const uint32_t key = q_ekey[e0 + e];
+    const uint32_t c = cell_number(cbase, key);
+    const uint32_t m = q_emass[e0 + e];
+    const uint32_t sh = (uint32_t)(top - (int)(key >> KEY_DEPTH_SHIFT));
+    const uint8_t h = hcell ? hcell[c] : (uint8_t)0xFFu;
+    if (h != 0xFFu) {
+      const uint32_t i = atomicAdd(&nh, 1u);
+      head[blockIdx.x * QP_HEAD_MAX + i] = make_uint2(m, (uint32_t)h | (sh << 8));
+    } else {
+      const uint32_t i = atomicAdd(&nl, 1u);
+      listed[e0 + i] = make_uint4(c, m, sh, 0u);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) counts[blockIdx.x] = make_uint2(nh, nl);
+}
+
 // Workgroup per (query, slice).  Workgroups are dealt to the 8 XCDs in turn,
 // so block b runs on XCD b % 8; slices are given out so that each XCD walks
 // one slice at a time through all the queries of the launch, keeping that
@@ -284,7 +318,8 @@ __global__ __launch_bounds__(QP_THREADS) __attribute__((amdgpu_num_sgpr(72))) vo
     int64_t n_cells, int64_t S, int64_t n_sl, const int64_t* __restrict__ d_eoff, const uint64_t* __restrict__ d_S,
     const uint32_t* __restrict__ d_S32, int64_t n_docs, const int64_t* __restrict__ q_eoff, const uint32_t* __restrict__ q_ekey,
     const uint32_t* __restrict__ q_emass, const uint64_t* __restrict__ q_S, int64_t r0, int64_t n_rows, int B, int H,
-    void* __restrict__ keys_out, unsigned long long* __restrict__ minmax) {
+    void* __restrict__ keys_out, unsigned long long* __restrict__ minmax, const uint2* __restrict__ q_counts,
+    const uint2* __restrict__ q_head, const uint4* __restrict__ q_listed) {
   static_assert(NARROW || !COMPACT, "compact keys need narrow counters");
   static_assert(NARROW || !HEAD, "dense head rows need narrow counters");
   using Acc = typename std::conditional<NARROW, uint32_t, unsigned long long>::type;
@@ -308,31 +343,14 @@ __global__ __launch_bounds__(QP_THREADS) __attribute__((amdgpu_num_sgpr(72))) vo
   const uint16_t* Pd = post_doc + d_eoff[d0];
   const uint32_t* Pm = post_mass + d_eoff[d0];
   const int64_t e0 = q_eoff[q];
-  const int ne = (int)(q_eoff[q + 1] - e0);
-  const int top = NARROW ? H : B;
   if constexpr (HEAD) {
-    // the query's head cells (any order: the sums are exact integers)
-    __shared__ uint32_t hq_mass[QP_HEAD_MAX];
-    __shared__ uint8_t hq_id[QP_HEAD_MAX], hq_sh[QP_HEAD_MAX];
-    __shared__ int n_hq;
-    if (tid == 0) n_hq = 0;
-    __syncthreads();
-    for (int e = tid; e < ne; e += QP_THREADS) {
-      const uint32_t key = q_ekey[e0 + e];
-      const uint8_t h = hcell[cell_number(cbase, key)];
-      if (h != 0xFFu) {
-        const int i = atomicAdd(&n_hq, 1);
-        hq_id[i] = h;
-        hq_mass[i] = q_emass[e0 + e];
-        hq_sh[i] = (uint8_t)(top - (int)(key >> KEY_DEPTH_SHIFT));
-      }
-    }
-    __syncthreads();
+    // the query's head cells, prepared once per call (row, mass, shift)
+    const uint2* hq = q_head + row * QP_HEAD_MAX;
     // thread t owns docs j * 2048 + 4t + k (j, k < 4): its row reads are
     // 16 bytes at consecutive addresses across the wavefront
     // (the cell's row, mass and shift are the same for every lane: scalars;
     // the rows are read at 32-bit byte offsets from the slice's base)
-    const int nh = n_hq;
+    const int nh = (int)__builtin_amdgcn_readfirstlane(q_counts[row].x);
     const char* rbase = reinterpret_cast<const char*>(head_rows + (size_t)sl * nhead * QP_HEAD_SLICE);
     const uint32_t lane_off = 16u * (uint32_t)tid;
     Acc a16[16];
@@ -344,9 +362,10 @@ __global__ __launch_bounds__(QP_THREADS) __attribute__((amdgpu_num_sgpr(72))) vo
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         const bool live = i + u < nh;
-        const uint32_t id = live ? __builtin_amdgcn_readfirstlane((uint32_t)hq_id[i + u]) : 0u;
-        am[u] = live ? __builtin_amdgcn_readfirstlane(hq_mass[i + u]) : 0u;
-        sh[u] = live ? __builtin_amdgcn_readfirstlane((uint32_t)hq_sh[i + u]) : 0u;
+        const uint2 hd = live ? hq[i + u] : make_uint2(0u, 0u);
+        const uint32_t id = __builtin_amdgcn_readfirstlane(hd.y & 0xFFu);
+        am[u] = __builtin_amdgcn_readfirstlane(hd.x);
+        sh[u] = __builtin_amdgcn_readfirstlane(hd.y >> 8);
         const uint32_t o = id * (uint32_t)(QP_HEAD_SLICE * 4) + lane_off;
 #pragma unroll
         for (int j = 0; j < 4; ++j)
@@ -372,19 +391,21 @@ __global__ __launch_bounds__(QP_THREADS) __attribute__((amdgpu_num_sgpr(72))) vo
   } else {
     for (int i = tid; i < nd; i += QP_THREADS) acc[i] = 0;
   }
-  for (int c0 = 0; c0 < ne; c0 += QP_ENTRIES) {
+  // the query's other cells, prepared once per call (cell number, mass, shift)
+  const int nl = (int)__builtin_amdgcn_readfirstlane(q_counts[row].y);
+  const uint4* ql = q_listed + e0;
+  for (int c0 = 0; c0 < nl; c0 += QP_ENTRIES) {
     if (tid == 0) ctr = 0ull;
     __syncthreads();
-    if (tid < QP_ENTRIES && c0 + tid < ne) {
-      const uint32_t key = q_ekey[e0 + c0 + tid];
-      const uint32_t c = cell_number(cbase, key);
-      const bool listed = !HEAD || hcell[c] == 0xFFu;
-      const uint32_t o1 = listed ? D[c] : 0u, o0 = listed && c ? D[c - 1] : 0u;
+    if (tid < QP_ENTRIES && c0 + tid < nl) {
+      const uint4 ent = ql[c0 + tid];
+      const uint32_t c = ent.x;
+      const uint32_t o1 = D[c], o0 = c ? D[c - 1] : 0u;
       if (o1 > o0) {
         const uint32_t len = o1 - o0, np = (len + QP_PIECE - 1) / QP_PIECE;
         const unsigned long long old = atomicAdd(&ctr, (1ull << 32) | np);
         const uint32_t idx = (uint32_t)(old >> 32);
-        items[idx] = make_uint4(o0, len, q_emass[e0 + c0 + tid], (uint32_t)top - (key >> KEY_DEPTH_SHIFT));
+        items[idx] = make_uint4(o0, len, ent.y, ent.z);
         pstart[idx] = (uint32_t)old;
       }
     }
@@ -748,6 +769,18 @@ void quadtree_knn_prepared(ft_index* ix, int64_t n_q, const int64_t* cand, int32
   uint64_t* keys = (uint64_t*)key_base;
   uint32_t* ckey_tmp = compact ? (uint32_t*)ix->ws_tiles.ensure(rows_per_chunk * k * 4) : nullptr;
   if (!cand) prepare_postings(ix, s);
+  // per-chunk query preparation for ranking all docs: counts and head cells
+  // per row, the other cells at the queries' own cell offsets
+  uint2* qp_counts = nullptr;
+  uint2* qp_head = nullptr;
+  uint4* qp_listed = nullptr;
+  if (!cand) {
+    const int64_t hb = (rows_per_chunk * 8 + 255) & ~int64_t(255), hh = rows_per_chunk * QP_HEAD_MAX * 8;
+    char* qp = (char*)ix->ws_misc.ensure(hb + hh + std::max<int64_t>(1, ix->qry.emb_nnz) * 16 + 16);
+    qp_counts = (uint2*)qp;
+    qp_head = (uint2*)(qp + hb);
+    qp_listed = (uint4*)(qp + hb + hh);
+  }
   hipStream_t s_sel = pipe ? ix->work : s;
   if (pipe) {
     FT_HIP(hipEventRecord(ix->ev_a, s));
@@ -782,6 +815,11 @@ void quadtree_knn_prepared(ft_index* ix, int64_t n_q, const int64_t* cand, int32
       // the buffers of chunk - 2 must have been read by its select (and
       // the key ranges emptied again)
       if (pipe && chunk >= 2) FT_HIP(hipStreamWaitEvent(s, ix->ev_sel[b], 0));
+      // the chunk's queries split into head and listed cells, once
+      k_qt_prep<<<(unsigned)rows, 256, 0, s>>>(
+          ix->qry.ecnt.as<int64_t>(), ix->qry.ekey.as<uint32_t>(), ix->qry.emass.as<uint32_t>(),
+          ix->post_cbase.as<uint32_t>(), ix->post_nhead > 0 ? ix->post_hcell.as<uint8_t>() : nullptr,
+          post_narrow(ix->Q, ix->height) ? ix->height : ix->B, r0, qp_counts, qp_head, qp_listed);
       auto go = [&](auto narrow, auto packed, auto head) {
         k_qt_post<decltype(narrow)::value, decltype(packed)::value, decltype(head)::value>
             <<<(unsigned)(groups * 8 * rows), QP_THREADS, 0, s>>>(
@@ -792,7 +830,7 @@ void quadtree_knn_prepared(ft_index* ix, int64_t n_q, const int64_t* cand, int32
             ix->post_slice, ix->post_nsl, ix->docs.ecnt.as<int64_t>(), ix->docs.S.as<uint64_t>(),
             ix->post_s32.as<uint32_t>(), n_cols,
             ix->qry.ecnt.as<int64_t>(), ix->qry.ekey.as<uint32_t>(), ix->qry.emass.as<uint32_t>(),
-            ix->qry.S.as<uint64_t>(), r0, rows, ix->B, ix->height, keys, minmax);
+            ix->qry.S.as<uint64_t>(), r0, rows, ix->B, ix->height, keys, minmax, qp_counts, qp_head, qp_listed);
       };
       const bool head = ix->post_nhead > 0;
       if (compact && head) go(std::true_type{}, std::true_type{}, std::true_type{});
