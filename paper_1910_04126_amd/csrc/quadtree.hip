@@ -330,7 +330,7 @@ __global__ __launch_bounds__(QP_THREADS) __attribute__((amdgpu_num_sgpr(72))) vo
   __shared__ uint32_t pstart[QP_ENTRIES];      // first piece of each list
   __shared__ uint8_t pitem[QP_MAX_PIECES];     // list of each piece
   __shared__ unsigned long long red[2][QP_WAVES];
-  __shared__ unsigned long long ctr;
+  __shared__ unsigned long long ctr[2];  // (items << 32 | pieces) of a round, two rounds in turn
   const int64_t blk = blockIdx.x;
   const int64_t local = blk >> 3;
   const int64_t grp = local / n_rows, row = local - grp * n_rows;
@@ -394,29 +394,30 @@ __global__ __launch_bounds__(QP_THREADS) __attribute__((amdgpu_num_sgpr(72))) vo
   // the query's other cells, prepared once per call (cell number, mass, shift)
   const int nl = (int)__builtin_amdgcn_readfirstlane(q_counts[row].y);
   const uint4* ql = q_listed + e0;
-  for (int c0 = 0; c0 < nl; c0 += QP_ENTRIES) {
-    if (tid == 0) ctr = 0ull;
-    __syncthreads();
+  // Rounds of up to QP_ENTRIES cells: the thread that finds a non-empty list
+  // claims its item and its pieces and writes their piece table entries
+  // itself; the round's counter was cleared during the previous round (the
+  // two counters alternate), so a round takes two barriers.
+  if (tid == 0) ctr[0] = ctr[1] = 0ull;
+  __syncthreads();
+  for (int c0 = 0, rnd = 0; c0 < nl; c0 += QP_ENTRIES, rnd ^= 1) {
     if (tid < QP_ENTRIES && c0 + tid < nl) {
       const uint4 ent = ql[c0 + tid];
       const uint32_t c = ent.x;
       const uint32_t o1 = D[c], o0 = c ? D[c - 1] : 0u;
       if (o1 > o0) {
         const uint32_t len = o1 - o0, np = (len + QP_PIECE - 1) / QP_PIECE;
-        const unsigned long long old = atomicAdd(&ctr, (1ull << 32) | np);
-        const uint32_t idx = (uint32_t)(old >> 32);
+        const unsigned long long old = atomicAdd(&ctr[rnd], (1ull << 32) | np);
+        const uint32_t idx = (uint32_t)(old >> 32), p0 = (uint32_t)old;
         items[idx] = make_uint4(o0, len, ent.y, ent.z);
-        pstart[idx] = (uint32_t)old;
+        pstart[idx] = p0;
+        for (uint32_t j = 0; j < np; ++j) pitem[p0 + j] = (uint8_t)idx;
       }
     }
     __syncthreads();
-    const unsigned long long cc = ctr;
-    const uint32_t n_items = (uint32_t)(cc >> 32), n_pieces = (uint32_t)cc;
-    for (uint32_t i = tid; i < n_items; i += QP_THREADS) {
-      const uint32_t p0 = pstart[i], np = (items[i].y + QP_PIECE - 1) / QP_PIECE;
-      for (uint32_t j = 0; j < np; ++j) pitem[p0 + j] = (uint8_t)i;
-    }
-    __syncthreads();
+    const unsigned long long cc = ctr[rnd];
+    if (tid == 0) ctr[rnd ^ 1] = 0ull;
+    const uint32_t n_pieces = (uint32_t)cc;
     // a piece belongs to one wavefront, so its list offset, length, query
     // mass and shift are scalars; the entries are read at 32-bit byte offsets
     // from the slice's list base, and a full piece (every piece of a list but
