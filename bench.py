@@ -50,7 +50,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 # rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a 1 GiB copy
 # (profiles/flowtree_quadtree_batched_hbm_traffic.md), valid while the kernel
 # sources hash to TRAFFIC_SOURCES_SHA1.
-TRAFFIC_BYTES = {"batched": 2.7731e+11, "batched_v1m": 4.1680e+11}
+TRAFFIC_BYTES = {"batched": 2.7755e+11, "batched_v1m": 4.1655e+11}
 TRAFFIC_SOURCES = ("paper_1910_04126_amd/csrc/flow.h", "paper_1910_04126_amd/csrc/flowtree.hip",
                    "paper_1910_04126_amd/csrc/wave.h", "paper_1910_04126_amd/csrc/common.h")
 TRAFFIC_SOURCES_SHA1 = "4c387ec6d488da7f3e0d48b278d4be487d7e8169"
@@ -71,11 +71,11 @@ def measured_traffic(workload):
 # WRITE_SIZE scaled by the 1 GiB copy), and the ranking kernel's LDS active
 # share of cycles, bank-conflict share of LDS cycles, VALU issue against the
 # 1.7 per CU-cycle that a VALU-only probe reaches, and L2 hit rate.
-PRUNE_COUNTERS = {"batched": {"bytes": 8.6800e+10, "lds_busy": 0.42, "lds_bank_conflict": 0.43,
-                              "valu_issue": 0.42, "l2_hit": 0.86}}
+PRUNE_COUNTERS = {"batched": {"bytes": 8.4245e+10, "lds_busy": 0.44, "lds_bank_conflict": 0.44,
+                              "valu_issue": 0.45, "l2_hit": 0.86}}
 PRUNE_SOURCES = ("paper_1910_04126_amd/csrc/quadtree.hip", "paper_1910_04126_amd/csrc/select.hip",
                  "paper_1910_04126_amd/csrc/wave.h", "paper_1910_04126_amd/csrc/common.h")
-PRUNE_SOURCES_SHA1 = "5ebb387884fa31907836748682641c8aa6bcc6ca"
+PRUNE_SOURCES_SHA1 = "0973549f1dea6656da3dded8e951103953d53741"
 
 
 def _sources_sha1(files):
