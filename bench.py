@@ -75,7 +75,7 @@ PRUNE_COUNTERS = {"batched": {"bytes": 8.4245e+10, "lds_busy": 0.44, "lds_bank_c
                               "valu_issue": 0.45, "l2_hit": 0.86}}
 PRUNE_SOURCES = ("paper_1910_04126_amd/csrc/quadtree.hip", "paper_1910_04126_amd/csrc/select.hip",
                  "paper_1910_04126_amd/csrc/wave.h", "paper_1910_04126_amd/csrc/common.h")
-PRUNE_SOURCES_SHA1 = "0973549f1dea6656da3dded8e951103953d53741"
+PRUNE_SOURCES_SHA1 = "8d732dce72eb83c73a589d17fa571f7117083ef4"
 
 
 def _sources_sha1(files):

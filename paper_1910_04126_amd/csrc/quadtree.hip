@@ -133,7 +133,7 @@ __global__ __launch_bounds__(QT_THREADS) void k_qt_tile(
 // partition the mass, so the sum is below 2^(Q + height)), else u64 in grid
 // units; either way they fill 32 KB, so a slice is 8192 or 4096 docs.  With
 // 128 cells per round and two pieces in flight a workgroup needs under 40 KB
-// of LDS and 46 VGPRs, so a CU holds four of them (8 wavefronts per SIMD):
+// of LDS and 52 VGPRs, so a CU holds four of them (8 wavefronts per SIMD):
 // the kernel spends most of its time waiting on list reads and LDS atomics.
 
 constexpr int QP_THREADS = 512;
