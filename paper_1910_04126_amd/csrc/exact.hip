@@ -114,14 +114,20 @@ __global__ void k_exact_scatter(int64_t n_pairs, const uint8_t* __restrict__ bkt
 
 constexpr uint16_t EX_NONE = 0xFFFF;
 
-// Per-item arrays for supports of at most NMAX items: 28 KB at 512 (five
-// workgroups per CU), 51 KB at FT_MAX_SUPPORT = 1024 (three).
+// Per-item arrays for supports of at most NMAX items: 25 KB at 512 (six
+// workgroups per CU), 50 KB at FT_MAX_SUPPORT = 1024 (three).
 template <int NMAX>
 struct ExactLds {
-  static_assert(2 * NMAX * sizeof(uint16_t) <= sizeof(BlockLds::tile), "level lists live in the block tile");
-  BlockLds blk;
+  // the distance blocks are needed only while a pair's distance matrix is
+  // built, the Dijkstra distances only after: they share their space
+  union {
+    BlockLds blk;
+    struct {
+      double ds[NMAX], dt[NMAX];  // Dijkstra distances (reduced costs)
+    } dj;
+  } u;
+  uint16_t bs[NMAX], bt[NMAX];  // the nodes of one distance level
   double ps[NMAX], pt[NMAX];  // potentials: doc items, query items
-  double ds[NMAX], dt[NMAX];  // Dijkstra distances (reduced costs)
   uint32_t es[NMAX], et[NMAX];  // supply / demand not yet moved
   uint16_t prs[NMAX], prt[NMAX];  // predecessor on the other side
   uint8_t vs[NMAX], vt[NMAX];  // settled
@@ -196,10 +202,10 @@ __global__ __launch_bounds__(64) void k_exact(ExactArgs a) {
       const int ni = min(32, nd - ib);
       for (int jb = 0; jb < nq; jb += 32) {
         const int nj = min(32, nq - jb);
-        block_d2(L.blk, a.rows, dr, qr, ib, ni, jb, nj);
+        block_d2(L.u.blk, a.rows, dr, qr, ib, ni, jb, nj);
         const int col = lane & 31;
         for (int r = lane >> 5; r < ni; r += 2)
-          if (col < nj) S[(int64_t)(ib + r) * nq + jb + col] = sqrtf(L.blk.tile[r][col]);
+          if (col < nj) S[(int64_t)(ib + r) * nq + jb + col] = sqrtf(L.u.blk.tile[r][col]);
         __syncthreads();
       }
     }
@@ -225,23 +231,22 @@ __global__ __launch_bounds__(64) void k_exact(ExactArgs a) {
       // smallest distance among its unsettled nodes
       double lmin = INFINITY;
       for (int i = lane; i < nd; i += 64) {
-        L.ds[i] = L.es[i] > 0 ? 0.0 : INFINITY;
+        L.u.dj.ds[i] = L.es[i] > 0 ? 0.0 : INFINITY;
         L.prs[i] = EX_NONE;
         L.vs[i] = 0;
-        lmin = fmin(lmin, L.ds[i]);
+        lmin = fmin(lmin, L.u.dj.ds[i]);
       }
       for (int j = lane; j < nq; j += 64) {
-        L.dt[j] = INFINITY;
+        L.u.dj.dt[j] = INFINITY;
         L.prt[j] = EX_NONE;
         L.vt[j] = 0;
       }
       __syncthreads();
       int target = -1;
       double dist_t = 0.0;
-      // the nodes settled at one distance level (ids, in index order), in
-      // the block tile, free after the distance pass
-      uint16_t* bs = reinterpret_cast<uint16_t*>(&L.blk.tile[0][0]);
-      uint16_t* bt = bs + NMAX;
+      // the nodes settled at one distance level (ids, in index order)
+      uint16_t* bs = L.bs;
+      uint16_t* bt = L.bt;
       const unsigned long long below = (1ull << lane) - 1ull;
       while (true) {
         // the level: the smallest distance of a node not yet settled
@@ -256,7 +261,7 @@ __global__ __launch_bounds__(64) void k_exact(ExactArgs a) {
         int nt = 0;
         for (int j0 = 0; j0 < nq; j0 += 64) {
           const int j = j0 + lane;
-          const bool eq = j < nq && !L.vt[j] && L.dt[j] == bd;
+          const bool eq = j < nq && !L.vt[j] && L.u.dj.dt[j] == bd;
           if (eq && L.et[j] > 0 && (uint32_t)j < tj) tj = (uint32_t)j;
           const unsigned long long m = __ballot(eq);
           if (eq) bt[nt + __popcll(m & below)] = (uint16_t)j;
@@ -272,7 +277,7 @@ __global__ __launch_bounds__(64) void k_exact(ExactArgs a) {
         int ns = 0;
         for (int i0 = 0; i0 < nd; i0 += 64) {
           const int i = i0 + lane;
-          const bool eq = i < nd && !L.vs[i] && L.ds[i] == bd;
+          const bool eq = i < nd && !L.vs[i] && L.u.dj.ds[i] == bd;
           const unsigned long long m = __ballot(eq);
           if (eq) {
             bs[ns + __popcll(m & below)] = (uint16_t)i;
@@ -287,7 +292,7 @@ __global__ __launch_bounds__(64) void k_exact(ExactArgs a) {
         // forward edges from the level's doc items
         for (int j = lane; j < nq; j += 64) {
           if (L.vt[j]) continue;
-          double best = L.dt[j];
+          double best = L.u.dj.dt[j];
           int pred = L.prt[j];
           const double pj = L.pt[j];
 #pragma unroll 4
@@ -300,14 +305,14 @@ __global__ __launch_bounds__(64) void k_exact(ExactArgs a) {
               pred = i;
             }
           }
-          L.dt[j] = best;
+          L.u.dj.dt[j] = best;
           L.prt[j] = (uint16_t)pred;
           lmin = fmin(lmin, best);
         }
         // backward edges from the level's query items, where a flow is positive
         for (int i = lane; i < nd; i += 64) {
           if (L.vs[i]) continue;
-          double best = L.ds[i];
+          double best = L.u.dj.ds[i];
           int pred = L.prs[i];
           const double pi = L.ps[i];
           for (int b = 0; b < nt; ++b) {
@@ -321,7 +326,7 @@ __global__ __launch_bounds__(64) void k_exact(ExactArgs a) {
               }
             }
           }
-          L.ds[i] = best;
+          L.u.dj.ds[i] = best;
           L.prs[i] = (uint16_t)pred;
           lmin = fmin(lmin, best);
         }
@@ -361,8 +366,8 @@ __global__ __launch_bounds__(64) void k_exact(ExactArgs a) {
       left -= L.delta;
       // potentials move by the distances, capped at the target's (nodes not
       // settled are at least that far)
-      for (int i = lane; i < nd; i += 64) L.ps[i] += fmin(L.ds[i], dist_t);
-      for (int j = lane; j < nq; j += 64) L.pt[j] += fmin(L.dt[j], dist_t);
+      for (int i = lane; i < nd; i += 64) L.ps[i] += fmin(L.u.dj.ds[i], dist_t);
+      for (int j = lane; j < nq; j += 64) L.pt[j] += fmin(L.u.dj.dt[j], dist_t);
       __syncthreads();
     }
     // the flow's cost, rows of query items in order
