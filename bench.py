@@ -48,9 +48,9 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 
 # HBM bytes of one launch of the persistent Flowtree graph per workload, from
 # rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a 1 GiB copy
-# (profiles/flowtree_quadtree_batched_hbm_traffic.md), valid while the kernel
-# sources hash to TRAFFIC_SOURCES_SHA1.
-TRAFFIC_BYTES = {"batched": 2.7755e+11, "batched_v1m": 4.1655e+11}
+# (profiles/flowtree_quadtree_batched_hbm_traffic.md, profiles/flowtree_exhaustive_hbm_traffic.md),
+# valid while the kernel sources hash to TRAFFIC_SOURCES_SHA1.
+TRAFFIC_BYTES = {"batched": 2.7755e+11, "batched_v1m": 4.1655e+11, "exhaustive": 3.7551e+12}
 TRAFFIC_SOURCES = ("paper_1910_04126_amd/csrc/flow.h", "paper_1910_04126_amd/csrc/flowtree.hip",
                    "paper_1910_04126_amd/csrc/wave.h", "paper_1910_04126_amd/csrc/common.h")
 TRAFFIC_SOURCES_SHA1 = "4c387ec6d488da7f3e0d48b278d4be487d7e8169"
